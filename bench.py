@@ -1,0 +1,149 @@
+#!/usr/bin/env python3
+"""Benchmark of the pseudo-transient topology-optimisation hot path on one GPU.
+
+A step is one design step of the 2D cantilever at 1024 x 512 cells: relaxation of
+the elastic state to rho <= 1e-6 (FP32 sweeps on corrections of an FP64 state,
+FP64 norms), the compliance sensitivity, and the phase-field update with the FP64
+volume-multiplier search.  The state is warm-started from the previous step as
+in the optimisation loop.  Inputs are synthetic (seeded problem generators) and
+resident on the GPU before timing starts.
+
+Prints one JSON line: APT cell-updates/s (cells x sweeps / wall time of the timed
+steps), the roofline of the dominant kernel (the FP32 correction sweep) from HIP
+events recorded by the library around its sweep blocks, and the oracle timed on
+the host cores on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+# Algorithmic bytes per cell and sweep of the 2D FP32 correction sweep: the two
+# state components read and written (16 B), the two velocity components read and
+# written (16 B), the cell modulus (4 B) and the two right-hand-side components (8 B).
+BYTES_PER_CELL_2D_FP32 = 44
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--nx", type=int, default=1024)
+    ap.add_argument("--ny", type=int, default=512)
+    ap.add_argument("--theta", type=float, default=1.0)
+    ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--cpu-sweeps", type=int, default=100)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-timing", action="store_true", help="skip the library's sweep-block events")
+    return ap.parse_args()
+
+
+def cpu_baseline(prob, phi0, sweeps):
+    """The oracle as it stands, on the host cores: `sweeps` damped-wave sweeps of
+    the full grid from rest, one sensitivity evaluation and one phase update."""
+    import numpy as np
+    from oracle import design
+
+    t0 = time.perf_counter()
+    res, _ = design.solve(phi0, prob, params=design.AptParams(theta=1.0, check_every=100), n_iter=sweeps)
+    g = design.sensitivity(res.u, phi0, prob)
+    design.phase_update(phi0, g, prob)
+    dt = time.perf_counter() - t0
+    cores = len(os.sched_getaffinity(0))
+    value = prob.ncell * sweeps / dt
+    return {"value": value, "unit": "cell-updates/s", "cores": 1, "cores_available": cores, "kind": "oracle",
+            "seconds": round(dt, 3),
+            "sample": f"{sweeps} sweeps from rest + 1 sensitivity + 1 phase update on the full "
+                      f"{prob.n[0]}x{prob.n[1]} grid (FP64 NumPy/SciPy, single-threaded sparse products)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
+                                   "(multi-GPU sharding is described in DESIGN.md, not implemented)"}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2509_06971_amd.api import Context
+
+    prob = W.cantilever2d(args.nx, args.ny)
+    phi0 = W.initial_phi(prob)
+    ctx = Context(prob, "fp32")
+    phi = torch.tensor(phi0.ravel(), dtype=torch.float32, device="cuda")
+    u = ctx.new_state(torch.float64)
+    v = ctx.new_state()
+    g = ctx.new_cells()
+    comp = torch.zeros(2, dtype=torch.float64, device="cuda")
+    apt = dict(theta=args.theta, tol=args.tol, check_every=100, refine=True)
+    records = []
+
+    def step():
+        st, si, pi, _ = ctx.step(phi, u, v, g, vol_frac=prob.vol_frac, compliance=comp, apt=apt)
+        return si[0], pi[0]
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    if not args.no_timing:
+        ctx.set_timing(True)
+    ms_blocks, sweeps_timed = 0.0, 0
+    total_sweeps = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        si, pi = step()
+        total_sweeps += si["iters"]
+        ms, n = ctx.last_sweep_ms()
+        ms_blocks += ms * n
+        sweeps_timed += n
+        records.append({"iters": si["iters"], "outer": si["outer"], "rho": si["rel_res"]})
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ncell = prob.ncell
+    value = ncell * total_sweeps / wall
+    out = {
+        "metric": "APT cell-updates/s + %HBM peak; time to converged design FP32 vs FP64",
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1000.0 * wall / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 sweeps, f64 state/norms",
+        "data": "synthetic",
+        "config": {"workload": f"cantilever2d_{args.nx}x{args.ny}", "cells": ncell, "theta": args.theta,
+                   "tol": args.tol, "sweeps_timed": total_sweeps,
+                   "compliance": comp[0].item()},
+    }
+    if sweeps_timed > 0:
+        sweep_ms = ms_blocks / sweeps_timed
+        bytes_per_sweep = BYTES_PER_CELL_2D_FP32 * ncell
+        achieved = bytes_per_sweep / (sweep_ms * 1e-3) / 1e9
+        out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                           "kernel": "el2d_kernel<float> (FP32 correction sweep)",
+                           "sweep_us": sweep_ms * 1e3, "bytes_per_sweep": bytes_per_sweep}
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(prob, phi0.astype(np.float32).astype(np.float64), args.cpu_sweeps)
+    out["records"] = records
+    ctx.close()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

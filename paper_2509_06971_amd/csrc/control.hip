@@ -1,0 +1,230 @@
+// Solve control on the device: material preparation (modulus per cell and the
+// largest modulus, which sets the pseudo-time step), per-design setup, the
+// check-sweep finalisation (residual norm, stop rule, divergence), and small
+// elementwise helpers.  Everything that decides when to stop runs in double and
+// in a fixed summation order, so repeated runs are bit-identical.
+#include "kernels.hpp"
+#include "material.hpp"
+
+namespace petto {
+namespace {
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void material_kernel(const T* __restrict__ phi, T* __restrict__ E,
+                                                          double* __restrict__ E64, const CellRange* ranges,
+                                                          int nphase, long phase_stride, double e0,
+                                                          double emin, double p, double ep0, double ep1,
+                                                          double ep2, double* partial_max, int bpd) {
+  __shared__ double red[kBlock / kWave];
+  const int d = blockIdx.y;
+  const CellRange R = ranges[d];
+  const double ep[3] = {ep0, ep1, ep2};
+  double mx = 0.0;
+  for (long c = (long)blockIdx.x * kBlock + threadIdx.x; c < R.n; c += (long)gridDim.x * kBlock) {
+    double dE[2];
+    const double e = modulus<T>(phi, R.off + c, phase_stride, nphase, e0, emin, p, ep, dE);
+    E[R.off + c] = (T)e;
+    if (E64 != nullptr) E64[R.off + c] = e;
+    mx = fmax(mx, e);
+  }
+  const double m = block_max(mx, red);
+  if (threadIdx.x == 0) partial_max[(long)d * bpd + blockIdx.x] = m;
+}
+
+__global__ void setup_kernel(SetupArgs A) {
+  const int d = blockIdx.x;
+  const int lane = threadIdx.x;
+  double mx = 0.0;
+  for (int b = lane; b < A.blocks_per_design; b += kWave) mx = fmax(mx, A.partial_max[(long)d * A.blocks_per_design + b]);
+  mx = wave_max(mx);
+  if (lane == 0) {
+    SolveState& s = A.st[d];
+    const double h = A.h[d];
+    const double mmax = mx * A.m0;
+    double dt = A.dt_user;
+    if (!(dt > 0.0)) {
+      dt = A.theta > 0.0 ? h * sqrt(A.theta / (2.0 * A.ndim * mmax)) : h * h / (2.0 * A.ndim * mmax);
+    }
+    double hd = h * h;
+    if (A.ndim == 3) hd *= h;
+    s.dt = dt;
+    s.theta = A.theta;
+    s.hd = hd;
+    s.a = A.theta / (A.theta + dt);
+    s.c = dt / ((A.theta + dt) * hd);
+    s.fnorm = A.fnorm[d];
+    s.tol = A.tol;
+    s.rho = INFINITY;
+    s.rho_first = INFINITY;
+    s.r_pde = INFINITY;
+    s.sumsq = 0.0;
+    s.iters = 0;
+    s.done = 0;
+    s.status = 0;
+    s.checks = 0;
+    s.max_iter = A.max_iter;
+    s.check_every = A.check_every;
+    s.replay = A.replay;
+    s.first_seen = 0;
+  }
+  if (d == 0 && lane == 0) {
+    A.ctl[0] = 0;
+    A.ctl[1] = 0;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void finalize_kernel(FinalizeArgs A) {
+  __shared__ int sh_flags[3];
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+  for (int d = w; d < A.ndes; d += kBlock / kWave) {
+    SolveState& s = A.st[d];
+    if (s.done) continue;
+    const int t0 = A.tile0 ? A.tile0[d] : 0;
+    const int t1 = A.tile0 ? A.tile0[d + 1] : A.ntile;
+    double acc = 0.0;
+    for (int t = t0 + lane; t < t1; t += kWave) acc += A.partial[t];
+    acc = wave_sum(acc);
+    if (lane == 0) {
+      const double rho = sqrt(acc) / s.fnorm;
+      s.sumsq = acc;
+      s.rho = rho;
+      s.r_pde = sqrt(acc) / s.hd / (double)A.ncell[d];
+      s.checks += 1;
+      // mode 0 checks the state the block's last sweep started from, after the
+      // block ran; mode 1 checks the state itself before the block's sweeps.
+      if (A.mode == 0) s.iters += s.check_every;
+      if (!s.first_seen) {
+        s.first_seen = 1;
+        s.rho_first = rho;
+      }
+      if (!isfinite(rho) || rho > A.div_factor * fmax(s.rho_first, s.tol)) {
+        s.status = -3;
+        s.done = 1;
+      } else if (!s.replay && rho <= s.tol) {
+        s.status = 0;
+        s.done = 1;
+      } else if (s.iters >= s.max_iter) {
+        s.status = s.replay ? 0 : 1;
+        s.done = 1;
+      } else if (A.mode == 1) {
+        s.iters += s.check_every;   // the sweeps of this block will run
+      }
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int all = 1, div = 0, nc = 0;
+    for (int d = 0; d < A.ndes; ++d) {
+      const SolveState& s = A.st[d];
+      all &= (s.done != 0);
+      div |= (s.status == -3);
+      nc |= (s.status == 1);
+    }
+    const int seq = A.ctl[0];
+    A.ctl[1] = all;
+    A.ctl[0] = seq + 1;
+    PollRecord* slot = &A.ring[seq % kRing];
+    slot->all_done = all;
+    slot->any_diverged = div;
+    slot->any_not_converged = nc;
+    slot->seq = seq;
+    __threadfence_system();
+  }
+  (void)sh_flags;
+}
+
+__global__ __launch_bounds__(kBlock) void dot_finalize_kernel(const double* pfu, const double* pen,
+                                                              const int* tile0, int ntile, int ndes,
+                                                              double* out) {
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+  for (int d = w; d < ndes; d += kBlock / kWave) {
+    const int t0 = tile0 ? tile0[d] : 0;
+    const int t1 = tile0 ? tile0[d + 1] : ntile;
+    double a = 0.0, b = 0.0;
+    for (int t = t0 + lane; t < t1; t += kWave) {
+      a += pfu[t];
+      b += pen[t];
+    }
+    a = wave_sum(a);
+    b = wave_sum(b);
+    if (lane == 0) {
+      out[2 * d] = a;
+      out[2 * d + 1] = b;
+    }
+  }
+}
+
+template <typename T>
+__global__ void fill_kernel(T* p, long n, T value) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) p[i] = value;
+}
+
+template <typename T>
+__global__ void copy_kernel(T* dst, const T* src, long n) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) dst[i] = src[i];
+}
+
+__global__ void fold_kernel(double* u, float* d, long n, const int* all_done) {
+  if (*all_done) return;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    u[i] += (double)d[i];
+    d[i] = 0.f;
+  }
+}
+
+inline int grid_for(long n) {
+  long b = (n + kBlock - 1) / kBlock;
+  if (b > 4096) b = 4096;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
+}  // namespace
+
+template <typename T>
+void launch_material(const T* phi, T* E, double* E64, const CellRange* ranges, int ndes, long max_cells,
+                     int nphase, long phase_stride, double e0, double emin, double p, const double* ep,
+                     double* partial_max, int blocks_per_design, hipStream_t s) {
+  (void)max_cells;
+  hipLaunchKernelGGL((material_kernel<T>), dim3(blocks_per_design, ndes), dim3(kBlock), 0, s, phi, E, E64,
+                     ranges, nphase, phase_stride, e0, emin, p, ep[0], ep[1], ep[2], partial_max,
+                     blocks_per_design);
+}
+
+void launch_setup(const SetupArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(setup_kernel, dim3(a.ndes), dim3(kWave), 0, s, a);
+}
+
+void launch_finalize(const FinalizeArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(kBlock), 0, s, a);
+}
+
+void launch_dot_finalize(const double* pfu, const double* pen, const int* tile0, int ntile, int ndes,
+                         double* out, hipStream_t s) {
+  hipLaunchKernelGGL(dot_finalize_kernel, dim3(1), dim3(kBlock), 0, s, pfu, pen, tile0, ntile, ndes, out);
+}
+
+template <typename T>
+void launch_fill(T* p, long n, T value, hipStream_t s) {
+  hipLaunchKernelGGL((fill_kernel<T>), dim3(grid_for(n)), dim3(kBlock), 0, s, p, n, value);
+}
+
+template <typename T>
+void launch_copy(T* dst, const T* src, long n, hipStream_t s) {
+  hipLaunchKernelGGL((copy_kernel<T>), dim3(grid_for(n)), dim3(kBlock), 0, s, dst, src, n);
+}
+
+void launch_fold(double* u, float* d, long n, const int* all_done, hipStream_t s) {
+  hipLaunchKernelGGL(fold_kernel, dim3(grid_for(n)), dim3(kBlock), 0, s, u, d, n, all_done);
+}
+
+template void launch_material<float>(const float*, float*, double*, const CellRange*, int, long, int, long,
+                                     double, double, double, const double*, double*, int, hipStream_t);
+template void launch_material<double>(const double*, double*, double*, const CellRange*, int, long, int, long,
+                                      double, double, double, const double*, double*, int, hipStream_t);
+template void launch_fill<float>(float*, long, float, hipStream_t);
+template void launch_fill<double>(double*, long, double, hipStream_t);
+template void launch_copy<float>(float*, const float*, long, hipStream_t);
+template void launch_copy<double>(double*, const double*, long, hipStream_t);
+
+}  // namespace petto

@@ -1,0 +1,1048 @@
+// Host side of the C ABI declared in include/petto.h: argument checks, device
+// workspace, and the orchestration of the relaxation (graph-captured blocks of
+// sweeps polled through a host-mapped ring), the FP32/FP64 refinement loop, the
+// sensitivity and the design update.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <functional>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+#include "petto.h"
+
+using namespace petto;
+
+namespace {
+
+thread_local std::string g_err;
+
+petto_status fail(petto_status s, const char* fmt, ...) {
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+#define HIP_TRY(expr)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess) return fail(PETTO_ERR_HIP, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+#define PETTO_TRY(expr)                    \
+  do {                                     \
+    petto_status s_ = (expr);              \
+    if (s_ < 0) return s_;                 \
+  } while (0)
+
+constexpr int kBpd = 256;          // material-kernel blocks per design
+constexpr int kMaxOuter = 64;      // refinement: correction solves per call
+constexpr double kDivFactor = 1e4;
+
+struct GraphEntry {
+  std::vector<const void*> key;
+  hipGraphExec_t exec = nullptr;
+};
+
+}  // namespace
+
+struct petto_ctx {
+  int physics = 0, ndim = 2, prec = 0, nprob = 1, nphase = 1;
+  std::vector<petto_problem> probs;
+  ElGeom geom{};                       // elastic (single design)
+  long nstate = 0;                     // elements of a state-layout buffer (all designs)
+  long ncell = 0;                      // cells of one phase (all designs)
+  std::vector<long> state_off, cell_off;
+  long max_cells = 0;
+  // problem data on the device
+  double* F64 = nullptr;               // load in double (state layout), nullptr for uniform heat
+  void* Ft = nullptr;                  // load in context precision
+  uint32_t* pins = nullptr;
+  HeatDesign* d_des = nullptr;
+  HeatTile* d_tiles = nullptr;
+  uint8_t* d_dir = nullptr;
+  int* d_tile0 = nullptr;
+  int ntile = 0;                       // heat: work-list length; elastic: partial slots
+  std::vector<HeatDesign> h_des;
+  CellRange* d_ranges = nullptr;
+  std::vector<CellRange> h_ranges;
+  long* d_ncell = nullptr;
+  double* d_fnorm = nullptr;
+  double* d_h = nullptr;
+  std::vector<double> fnorm;
+  double m0 = 1.0;
+  // workspace
+  void* ualt = nullptr;
+  void* E = nullptr;
+  double* E64 = nullptr;
+  float* d32a = nullptr;
+  float* d32b = nullptr;
+  float* b32 = nullptr;
+  double* partial = nullptr;
+  double* partial2 = nullptr;
+  double* partial_max = nullptr;
+  SolveState* st = nullptr;
+  int* ctl = nullptr;
+  PollRecord* ring_host = nullptr;
+  PollRecord* ring_dev = nullptr;
+  double* phase_scal = nullptr;
+  double* phase_work = nullptr;
+  double* phase_partial = nullptr;
+  double* comp = nullptr;
+  hipStream_t cap_stream = nullptr;
+  hipEvent_t ev_end[kRing] = {};
+  hipEvent_t ev_beg[kRing] = {};
+  bool events = false;
+  std::vector<GraphEntry> graphs;
+  bool timing = false;
+  double timed_ms = 0.0;
+  int64_t timed_sweeps = 0;
+  std::vector<void*> allocations;
+};
+
+namespace {
+
+size_t elem_size(const petto_ctx* c) { return c->prec == PETTO_FP64 ? sizeof(double) : sizeof(float); }
+
+petto_status dalloc(petto_ctx* c, void** p, size_t bytes) {
+  if (bytes == 0) bytes = 16;
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) return fail(PETTO_ERR_OOM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+  c->allocations.push_back(*p);
+  return PETTO_OK;
+}
+
+template <typename P>
+petto_status dalloc_t(petto_ctx* c, P** p, size_t count) {
+  void* v = nullptr;
+  petto_status s = dalloc(c, &v, count * sizeof(P));
+  *p = static_cast<P*>(v);
+  return s;
+}
+
+template <typename P>
+petto_status upload(petto_ctx* c, P** p, const std::vector<P>& h) {
+  PETTO_TRY(dalloc_t(c, p, h.size()));
+  if (!h.empty()) HIP_TRY(hipMemcpy(*p, h.data(), h.size() * sizeof(P), hipMemcpyHostToDevice));
+  return PETTO_OK;
+}
+
+long padded_state(const petto_problem& p) {
+  long n = 1;
+  for (int a = 0; a < p.ndim; ++a) n *= (long)p.n[a] + 1;
+  return n * p.ndim;
+}
+
+long cells(const petto_problem& p) {
+  long n = 1;
+  for (int a = 0; a < p.ndim; ++a) n *= p.n[a];
+  return n;
+}
+
+// canonical flat index of component a at (i, j, k)
+long sidx(const petto_problem& p, int a, long i, long j, long k) {
+  const long px = p.n[0] + 1, py = p.n[1] + 1;
+  const long pz = p.ndim == 3 ? p.n[2] + 1 : 1;
+  return (long)a * px * py * pz + (k * py + j) * px + i;
+}
+
+bool is_finite(double x) { return std::isfinite(x); }
+
+petto_status validate_problem(const petto_problem& p, int idx) {
+  if (p.physics != PETTO_ELASTIC && p.physics != PETTO_HEAT)
+    return fail(PETTO_ERR_INVALID, "problem %d: physics must be PETTO_ELASTIC or PETTO_HEAT", idx);
+  if (p.ndim != 2 && p.ndim != 3) return fail(PETTO_ERR_INVALID, "problem %d: ndim must be 2 or 3", idx);
+  for (int a = 0; a < p.ndim; ++a) {
+    if (p.n[a] < 2 || p.n[a] > (1 << 16))
+      return fail(PETTO_ERR_INVALID, "problem %d: n[%d]=%d outside [2, 65536]", idx, a, p.n[a]);
+  }
+  if (!(p.h > 0.0) || !is_finite(p.h)) return fail(PETTO_ERR_INVALID, "problem %d: h must be positive", idx);
+  if (p.nphase != 1 && p.nphase != 2) return fail(PETTO_ERR_INVALID, "problem %d: nphase must be 1 or 2", idx);
+  if (!(p.p >= 1.0) || !is_finite(p.p)) return fail(PETTO_ERR_INVALID, "problem %d: penalty p must be >= 1", idx);
+  if (p.nphase == 1) {
+    if (!(p.e0 > 0.0) || !(p.emin >= 0.0) || !(p.emin < p.e0) || !is_finite(p.e0))
+      return fail(PETTO_ERR_INVALID, "problem %d: need 0 <= emin < e0", idx);
+  } else {
+    if (p.physics != PETTO_ELASTIC) return fail(PETTO_ERR_INVALID, "problem %d: nphase 2 is elastic only", idx);
+    for (int m = 0; m < 3; ++m)
+      if (!(p.e_phase[m] >= 0.0) || !is_finite(p.e_phase[m]))
+        return fail(PETTO_ERR_INVALID, "problem %d: e_phase[%d] must be >= 0", idx, m);
+    if (!(p.e_phase[0] > 0.0)) return fail(PETTO_ERR_INVALID, "problem %d: e_phase[0] must be > 0", idx);
+  }
+  if (p.physics == PETTO_ELASTIC) {
+    if (!(p.nu >= 0.0 && p.nu < 0.5)) return fail(PETTO_ERR_INVALID, "problem %d: nu must be in [0, 0.5)", idx);
+    for (int s = 0; s < 2 * p.ndim; ++s)
+      if (p.side[s] < 0 || p.side[s] > 2) return fail(PETTO_ERR_INVALID, "problem %d: side[%d] invalid", idx, s);
+    if (p.load == nullptr) return fail(PETTO_ERR_INVALID, "problem %d: elastic problem needs a load", idx);
+  } else {
+    if (p.fixed == nullptr) return fail(PETTO_ERR_INVALID, "problem %d: heat problem needs Dirichlet faces", idx);
+    if (p.load == nullptr && !is_finite(p.q)) return fail(PETTO_ERR_INVALID, "problem %d: q must be finite", idx);
+  }
+  return PETTO_OK;
+}
+
+// Elastic: check the mask against the sides, build the extra-pin bitmask and the load.
+petto_status prepare_elastic(petto_ctx* c, const petto_problem& p, std::vector<uint32_t>& pins_words,
+                             bool& any_pin, std::vector<double>& F) {
+  const long ns = padded_state(p);
+  const int nx = p.n[0], ny = p.n[1], nz = p.ndim == 3 ? p.n[2] : 1;
+  const int n3[3] = {nx, ny, nz};
+  std::vector<uint8_t> valid(ns, 0), side_fixed(ns, 0);
+  for (int a = 0; a < p.ndim; ++a)
+    for (int k = 0; k < (p.ndim == 3 ? nz + 1 : 1); ++k)
+      for (int j = 0; j <= ny; ++j)
+        for (int i = 0; i <= nx; ++i) {
+          const int id[3] = {i, j, k};
+          bool ok = true;
+          for (int b = 0; b < p.ndim; ++b) {
+            if (b == a) continue;
+            if (id[b] >= n3[b]) ok = false;
+          }
+          if (!ok) continue;
+          const long q = sidx(p, a, i, j, k);
+          valid[q] = 1;
+          if ((id[a] == 0 && p.side[2 * a] != PETTO_SIDE_FREE) || (id[a] == n3[a] && p.side[2 * a + 1] != PETTO_SIDE_FREE))
+            side_fixed[q] = 1;
+        }
+  pins_words.assign((ns + 31) / 32, 0u);
+  any_pin = false;
+  long nfixed = 0;
+  for (long q = 0; q < ns; ++q) {
+    const bool f = p.fixed != nullptr && p.fixed[q] != 0;
+    if (f && !valid[q]) return fail(PETTO_ERR_INVALID, "fixed mask marks padding slot %ld", q);
+    if (side_fixed[q] && p.fixed != nullptr && !f)
+      return fail(PETTO_ERR_INVALID, "fixed mask misses the normal unknown %ld of a clamped/roller side", q);
+    if (f && !side_fixed[q]) {
+      pins_words[q >> 5] |= 1u << (q & 31);
+      any_pin = true;
+    }
+    if (f || side_fixed[q]) ++nfixed;
+  }
+  if (nfixed == 0) return fail(PETTO_ERR_INVALID, "elastic problem has no Dirichlet unknown (rigid modes)");
+  F.assign(ns, 0.0);
+  double ss = 0.0;
+  for (long q = 0; q < ns; ++q) {
+    const double v = p.load[q];
+    if (!is_finite(v)) return fail(PETTO_ERR_INVALID, "load is not finite at %ld", q);
+    if (!valid[q] || side_fixed[q] || (p.fixed && p.fixed[q])) continue;
+    F[q] = v;
+    ss += v * v;
+  }
+  if (!(ss > 0.0)) return fail(PETTO_ERR_INVALID, "elastic load is zero on the free unknowns");
+  c->fnorm.push_back(std::sqrt(ss));
+  return PETTO_OK;
+}
+
+petto_status check_heat_mask(const petto_problem& p, int idx) {
+  const int nx = p.n[0], ny = p.n[1];
+  long nd = 0;
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i) {
+      const uint8_t b = p.fixed[(long)j * nx + i];
+      if ((b & 1) && i != 0) return fail(PETTO_ERR_INVALID, "problem %d: -x Dirichlet bit on interior cell", idx);
+      if ((b & 2) && i != nx - 1) return fail(PETTO_ERR_INVALID, "problem %d: +x Dirichlet bit on interior cell", idx);
+      if ((b & 4) && j != 0) return fail(PETTO_ERR_INVALID, "problem %d: -y Dirichlet bit on interior cell", idx);
+      if ((b & 8) && j != ny - 1) return fail(PETTO_ERR_INVALID, "problem %d: +y Dirichlet bit on interior cell", idx);
+      if (b & 0xF0) return fail(PETTO_ERR_INVALID, "problem %d: unknown Dirichlet bits", idx);
+      nd += (b & 1) + ((b >> 1) & 1) + ((b >> 2) & 1) + ((b >> 3) & 1);
+    }
+  if (nd == 0) return fail(PETTO_ERR_INVALID, "problem %d: heat design has no Dirichlet face", idx);
+  return PETTO_OK;
+}
+
+void destroy_graphs(petto_ctx* c) {
+  for (auto& g : c->graphs)
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  c->graphs.clear();
+}
+
+petto_status ensure_events(petto_ctx* c) {
+  if (c->events) return PETTO_OK;
+  for (int i = 0; i < kRing; ++i) {
+    HIP_TRY(hipEventCreate(&c->ev_end[i]));
+    HIP_TRY(hipEventCreate(&c->ev_beg[i]));
+  }
+  c->events = true;
+  return PETTO_OK;
+}
+
+// Enqueue one block of sweeps either through a cached graph (captured on the
+// context's private stream, replayed on the caller's) or directly.
+petto_status enqueue_block(petto_ctx* c, hipStream_t stream, bool use_graph, const std::vector<const void*>& key,
+                           const std::function<void(hipStream_t)>& body) {
+  if (!use_graph) {
+    body(stream);
+    HIP_TRY(hipGetLastError());
+    return PETTO_OK;
+  }
+  for (auto& g : c->graphs) {
+    if (g.key == key) {
+      HIP_TRY(hipGraphLaunch(g.exec, stream));
+      return PETTO_OK;
+    }
+  }
+  if (c->cap_stream == nullptr) HIP_TRY(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+  HIP_TRY(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+  body(c->cap_stream);
+  hipError_t le = hipGetLastError();
+  hipGraph_t graph = nullptr;
+  hipError_t ee = hipStreamEndCapture(c->cap_stream, &graph);
+  if (le != hipSuccess) return fail(PETTO_ERR_HIP, "kernel launch during capture failed: %s", hipGetErrorString(le));
+  if (ee != hipSuccess) return fail(PETTO_ERR_HIP, "hipStreamEndCapture failed: %s", hipGetErrorString(ee));
+  hipGraphExec_t exec = nullptr;
+  hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (ie != hipSuccess) return fail(PETTO_ERR_HIP, "hipGraphInstantiate failed: %s", hipGetErrorString(ie));
+  if (c->graphs.size() >= 16) {
+    (void)hipGraphExecDestroy(c->graphs.front().exec);
+    c->graphs.erase(c->graphs.begin());
+  }
+  c->graphs.push_back({key, exec});
+  HIP_TRY(hipGraphLaunch(exec, stream));
+  return PETTO_OK;
+}
+
+// Run blocks until the finalize kernel reports every design done.  Two blocks are
+// kept in flight; a block enqueued after the stop finds the done flags set and its
+// kernels return at once.  Blocks timed (when enabled) are those up to the stop.
+petto_status run_blocks(petto_ctx* c, hipStream_t stream, bool use_graph, const std::vector<const void*>& key,
+                        const std::function<void(hipStream_t)>& body, int sweeps_per_block, PollRecord* last) {
+  PETTO_TRY(ensure_events(c));
+  long launched = 0, checked = 0;
+  std::vector<float> block_ms;
+  for (;;) {
+    while (launched - checked < 2) {
+      if (c->timing) HIP_TRY(hipEventRecord(c->ev_beg[launched % kRing], stream));
+      PETTO_TRY(enqueue_block(c, stream, use_graph, key, body));
+      HIP_TRY(hipEventRecord(c->ev_end[launched % kRing], stream));
+      ++launched;
+    }
+    HIP_TRY(hipEventSynchronize(c->ev_end[checked % kRing]));
+    volatile PollRecord* r = &c->ring_host[checked % kRing];
+    const PollRecord rec{r->all_done, r->any_diverged, r->any_not_converged, r->seq};
+    if (rec.seq != (int)(checked % 0x7fffffff)) {
+      (void)hipStreamSynchronize(stream);
+      return fail(PETTO_ERR_HIP, "poll ring out of step (seq %d, expected %ld)", rec.seq, checked);
+    }
+    if (c->timing) {
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, c->ev_beg[checked % kRing], c->ev_end[checked % kRing]));
+      c->timed_ms += ms;
+      c->timed_sweeps += sweeps_per_block;
+    }
+    ++checked;
+    if (rec.all_done) {
+      *last = rec;
+      break;
+    }
+  }
+  HIP_TRY(hipStreamSynchronize(stream));
+  return PETTO_OK;
+}
+
+petto_status check_apt_params(const petto_ctx* c, const petto_apt_params* p) {
+  if (p == nullptr) return fail(PETTO_ERR_INVALID, "apt params are NULL");
+  if (!(p->theta >= 0.0) || !is_finite(p->theta)) return fail(PETTO_ERR_INVALID, "theta must be >= 0");
+  if (!is_finite(p->dt)) return fail(PETTO_ERR_INVALID, "dt must be finite (<= 0 selects the default)");
+  if (p->check_every < 2 || (p->check_every & 1))
+    return fail(PETTO_ERR_INVALID, "check_every must be even and >= 2");
+  if (p->max_iter < p->check_every) return fail(PETTO_ERR_INVALID, "max_iter must be >= check_every");
+  if (p->replay_iters < 0 || (p->replay_iters % p->check_every) != 0)
+    return fail(PETTO_ERR_INVALID, "replay_iters must be a nonnegative multiple of check_every");
+  if (p->replay_iters == 0 && !(p->tol > 0.0)) return fail(PETTO_ERR_INVALID, "tol must be > 0");
+  if (p->refine) {
+    if (c->prec != PETTO_FP32) return fail(PETTO_ERR_INVALID, "refine applies to FP32 contexts only");
+    if (p->replay_iters) return fail(PETTO_ERR_INVALID, "replay_iters cannot be combined with refine");
+  }
+  return PETTO_OK;
+}
+
+// ------------------------------------------------------------------------------ sweep bodies
+
+// nchk sweeps ping-ponging u <-> ualt (nchk even: the result lands in u).  With
+// `check`, the last one also sums r^2 for the finalize kernel.
+template <typename T>
+void elastic_sweeps(const petto_ctx* c, hipStream_t s, T* u, T* ualt, T* v, const T* E, const T* b,
+                    SolveState* st, int nchk, bool check = false) {
+  ElSweep<T> a{};
+  a.v = v;
+  a.E = E;
+  a.b = b;
+  a.st = st;
+  a.partial = c->partial;
+  for (int q = 0; q < nchk; ++q) {
+    a.uin = (q & 1) ? ualt : u;
+    a.uout = (q & 1) ? u : ualt;
+    const bool chk = check && q == nchk - 1;
+    if (c->ndim == 2) {
+      if (chk) launch_el2d<T, kCheck>(c->geom, a, s);
+      else launch_el2d<T, kSweep>(c->geom, a, s);
+    } else {
+      if (chk) launch_el3d<T, kCheck>(c->geom, a, s);
+      else launch_el3d<T, kSweep>(c->geom, a, s);
+    }
+  }
+}
+
+template <typename T>
+void heat_sweeps(const petto_ctx* c, hipStream_t s, T* u, T* ualt, T* v, const T* k, const T* b,
+                 SolveState* st, int nchk, bool check = false) {
+  HeatSweep<T> a{};
+  a.v = v;
+  a.k = k;
+  a.b = b;
+  a.des = c->d_des;
+  a.tiles = c->d_tiles;
+  a.dir = c->d_dir;
+  a.st = st;
+  a.all_done = c->ctl + 1;
+  a.partial = c->partial;
+  a.ntile = c->ntile;
+  for (int q = 0; q < nchk; ++q) {
+    a.uin = (q & 1) ? ualt : u;
+    a.uout = (q & 1) ? u : ualt;
+    if (check && q == nchk - 1) launch_heat2d<T, kCheck>(a, s);
+    else launch_heat2d<T, kSweep>(a, s);
+  }
+}
+
+int el_tiles_for(const petto_ctx* c, bool fp64) {
+  if (c->ndim == 2) return el2d_tiles(c->geom);
+  return el3d_tiles_prec(c->geom, fp64);   // 3D tiles depend on the kernel precision
+}
+
+void finalize(const petto_ctx* c, hipStream_t s, SolveState* st, bool fp64_tiles, int mode) {
+  FinalizeArgs f{};
+  f.st = st;
+  f.partial = c->partial;
+  f.tile0 = c->physics == PETTO_HEAT ? c->d_tile0 : nullptr;
+  f.ntile = c->physics == PETTO_HEAT ? c->ntile : el_tiles_for(c, fp64_tiles);
+  f.ndes = c->nprob;
+  f.ncell = c->d_ncell;
+  f.ctl = c->ctl;
+  f.ring = c->ring_dev;
+  f.mode = mode;
+  f.div_factor = kDivFactor;
+  launch_finalize(f, s);
+}
+
+template <typename T>
+petto_status material(petto_ctx* c, const void* phi, hipStream_t s, bool with64) {
+  const double ep[3] = {c->probs[0].e_phase[0], c->probs[0].e_phase[1], c->probs[0].e_phase[2]};
+  const petto_problem& p = c->probs[0];
+  launch_material<T>(static_cast<const T*>(phi), static_cast<T*>(c->E), with64 ? c->E64 : nullptr, c->d_ranges,
+                     c->nprob, c->max_cells, c->nphase, c->ncell, p.e0, p.emin, p.p, ep, c->partial_max, kBpd, s);
+  HIP_TRY(hipGetLastError());
+  return PETTO_OK;
+}
+
+petto_status setup(petto_ctx* c, hipStream_t s, SolveState* st, const petto_apt_params* ap, double tol, int replay,
+                   int max_iter) {
+  SetupArgs a{};
+  a.st = st;
+  a.partial_max = c->partial_max;
+  a.blocks_per_design = kBpd;
+  a.ndes = c->nprob;
+  a.fnorm = c->d_fnorm;
+  a.h = c->d_h;
+  a.m0 = c->m0;
+  a.ndim = c->ndim;
+  a.theta = ap->theta;
+  a.dt_user = ap->dt;
+  a.tol = tol;
+  a.max_iter = max_iter;
+  a.check_every = ap->check_every;
+  a.replay = replay;
+  a.ctl = c->ctl;
+  launch_setup(a, s);
+  HIP_TRY(hipGetLastError());
+  return PETTO_OK;
+}
+
+petto_status read_states(petto_ctx* c, SolveState* dev, std::vector<SolveState>& h, hipStream_t s) {
+  h.resize(c->nprob);
+  HIP_TRY(hipMemcpyAsync(h.data(), dev, sizeof(SolveState) * c->nprob, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return PETTO_OK;
+}
+
+petto_status status_of(const std::vector<SolveState>& h) {
+  petto_status worst = PETTO_OK;
+  for (const auto& s : h) {
+    if (s.status == -3) return fail(PETTO_ERR_DIVERGED, "relaxation diverged (residual non-finite or grew 1e4x)");
+    if (s.status == 1) worst = PETTO_NOT_CONVERGED;
+  }
+  return worst;
+}
+
+// Plain relaxation in the context precision.
+template <typename T>
+petto_status solve_plain(petto_ctx* c, const void* phi, void* u, void* v, const petto_apt_params* ap,
+                         hipStream_t s, petto_solve_info* info) {
+  PETTO_TRY(material<T>(c, phi, s, false));
+  const int replay = ap->replay_iters > 0;
+  PETTO_TRY(setup(c, s, c->st, ap, replay ? -1.0 : ap->tol, replay, replay ? ap->replay_iters : ap->max_iter));
+  launch_fill<T>(static_cast<T*>(v), c->nstate, T(0), s);
+  HIP_TRY(hipGetLastError());
+  T* uu = static_cast<T*>(u);
+  T* ua = static_cast<T*>(c->ualt);
+  T* vv = static_cast<T*>(v);
+  const T* E = static_cast<const T*>(c->E);
+  const T* b = static_cast<const T*>(c->Ft);
+  const int nchk = ap->check_every;
+  std::function<void(hipStream_t)> body = [=](hipStream_t st) {
+    if (c->physics == PETTO_ELASTIC) elastic_sweeps<T>(c, st, uu, ua, vv, E, b, c->st, nchk, true);
+    else heat_sweeps<T>(c, st, uu, ua, vv, E, b, c->st, nchk, true);
+    finalize(c, st, c->st, sizeof(T) == 8, 0);
+  };
+  std::vector<const void*> key = {uu, ua, vv, E, b, (const void*)(long)nchk, (const void*)(long)sizeof(T),
+                                  (const void*)1};
+  PollRecord last{};
+  PETTO_TRY(run_blocks(c, s, ap->use_graph != 0, key, body, nchk, &last));
+  std::vector<SolveState> h;
+  PETTO_TRY(read_states(c, c->st, h, s));
+  if (info) {
+    for (int d = 0; d < c->nprob; ++d) {
+      info[d].iters = h[d].iters;
+      info[d].status = h[d].status == -3 ? PETTO_ERR_DIVERGED : h[d].status == 1 ? PETTO_NOT_CONVERGED : PETTO_OK;
+      info[d].outer = 0;
+      info[d].rel_res = h[d].rho;
+      info[d].r_pde = h[d].r_pde;
+      info[d].dt = h[d].dt;
+    }
+  }
+  return status_of(h);
+}
+
+// FP32 sweeps on a correction d of a double state u.  Each block: fold the
+// correction into u (u += d, d = 0), form r = F - K u in double (rounded to float
+// as the sweeps' right-hand side), check ||r|| / ||F|| against tol, then run
+// check_every FP32 sweeps on K d = r with the velocity carried over.  In exact
+// arithmetic the pair (u + d, v) follows the plain iteration.
+petto_status solve_refine(petto_ctx* c, const void* phi, void* u, void* v, const petto_apt_params* ap,
+                          hipStream_t s, petto_solve_info* info) {
+  PETTO_TRY(material<float>(c, phi, s, true));
+  PETTO_TRY(setup(c, s, c->st, ap, ap->tol, 0, ap->max_iter));
+  double* u64 = static_cast<double*>(u);
+  float* v32 = static_cast<float*>(v);
+  float* da = c->d32a;
+  float* db = c->d32b;
+  launch_fill<float>(v32, c->nstate, 0.f, s);
+  launch_fill<float>(da, c->nstate, 0.f, s);
+  HIP_TRY(hipGetLastError());
+  const int nchk = ap->check_every;
+  const float* E = static_cast<const float*>(c->E);
+  const float* b = c->b32;
+  std::function<void(hipStream_t)> body = [=](hipStream_t st) {
+    launch_fold(u64, da, c->nstate, c->ctl + 1, st);
+    if (c->physics == PETTO_ELASTIC) {
+      ElSweep<double> a{};
+      a.uin = u64;
+      a.E = c->E64;
+      a.b = c->F64;
+      a.st = c->st;
+      a.partial = c->partial;
+      a.b32 = c->b32;
+      if (c->ndim == 2) launch_el2d<double, kRefine>(c->geom, a, st);
+      else launch_el3d<double, kRefine>(c->geom, a, st);
+    } else {
+      HeatSweep<double> a{};
+      a.uin = u64;
+      a.k = c->E64;
+      a.b = c->F64;
+      a.des = c->d_des;
+      a.tiles = c->d_tiles;
+      a.dir = c->d_dir;
+      a.st = c->st;
+      a.all_done = c->ctl + 1;
+      a.partial = c->partial;
+      a.b32 = c->b32;
+      a.ntile = c->ntile;
+      launch_heat2d<double, kRefine>(a, st);
+    }
+    finalize(c, st, c->st, true, 1);
+    if (c->physics == PETTO_ELASTIC) elastic_sweeps<float>(c, st, da, db, v32, E, b, c->st, nchk);
+    else heat_sweeps<float>(c, st, da, db, v32, E, b, c->st, nchk);
+  };
+  std::vector<const void*> key = {u64, da, db, v32, E, b, (const void*)(long)nchk, (const void*)2};
+  PollRecord last{};
+  PETTO_TRY(run_blocks(c, s, ap->use_graph != 0, key, body, nchk, &last));
+  std::vector<SolveState> h;
+  PETTO_TRY(read_states(c, c->st, h, s));
+  if (info) {
+    for (int d = 0; d < c->nprob; ++d) {
+      info[d].iters = h[d].iters;
+      info[d].status = h[d].status == -3 ? PETTO_ERR_DIVERGED : h[d].status == 1 ? PETTO_NOT_CONVERGED : PETTO_OK;
+      info[d].outer = h[d].checks;
+      info[d].rel_res = h[d].rho;
+      info[d].r_pde = h[d].r_pde;
+      info[d].dt = h[d].dt;
+    }
+  }
+  return status_of(h);
+}
+
+template <typename U, typename T>
+void adjoint_launch(petto_ctx* c, const void* phi, const void* u, const void* w, void* grad, hipStream_t s) {
+  const petto_problem& p = c->probs[0];
+  if (c->physics == PETTO_ELASTIC) {
+    ElAdjoint<U, T> a{};
+    a.u = static_cast<const U*>(u);
+    a.w = static_cast<const U*>(w ? w : u);
+    a.phi = static_cast<const T*>(phi);
+    a.grad = static_cast<T*>(grad);
+    a.F = c->F64;
+    a.partial_fu = c->partial;
+    a.partial_en = c->partial2;
+    a.nphase = c->nphase;
+    a.e0 = p.e0;
+    a.emin = p.emin;
+    a.p = p.p;
+    for (int m = 0; m < 3; ++m) a.ep[m] = p.e_phase[m];
+    if (c->ndim == 2) launch_el2d_adjoint<U, T>(c->geom, a, s);
+    else launch_el3d_adjoint<U, T>(c->geom, a, s);
+  } else {
+    HeatAdjoint<U, T> a{};
+    a.u = static_cast<const U*>(u);
+    a.w = static_cast<const U*>(w ? w : u);
+    a.phi = static_cast<const T*>(phi);
+    a.grad = static_cast<T*>(grad);
+    a.F = c->F64;
+    a.des = c->d_des;
+    a.tiles = c->d_tiles;
+    a.dir = c->d_dir;
+    a.partial_fu = c->partial;
+    a.partial_en = c->partial2;
+    a.e0 = p.e0;
+    a.emin = p.emin;
+    a.p = p.p;
+    a.ntile = c->ntile;
+    launch_heat2d_adjoint<U, T>(a, s);
+  }
+}
+
+template <typename T>
+petto_status phase_update_impl(petto_ctx* c, void* phi, const void* grad, const petto_phase_params* pp,
+                               hipStream_t s, petto_phase_info* info) {
+  T* ph = static_cast<T*>(phi);
+  const T* g = static_cast<const T*>(grad);
+  const int passes = pp->bisect_passes > 0 ? pp->bisect_passes : 9;
+  for (int d = 0; d < c->nprob; ++d) {
+    const CellRange& R = c->h_ranges[d];
+    const double h = R.h;
+    double dt_ac = pp->dt_ac;
+    if (!(dt_ac > 0.0)) {
+      const double pi = 3.141592653589793;
+      dt_ac = pp->gamma > 0.0 ? 0.9 * std::fmin(h * h / (4.0 * c->ndim * pp->gamma), 32.0 / (pi * pi))
+                              : 0.9 * 32.0 / (pi * pi);
+    }
+    for (int m = 0; m < c->nphase; ++m) {
+      PhaseArgs<T> a{};
+      a.phi = ph + (long)m * c->ncell + R.off;
+      a.g = g + (long)m * c->ncell + R.off;
+      a.prev = m == 0 ? nullptr : ph + R.off;
+      a.work = c->phase_work;
+      a.partial = c->phase_partial;
+      a.scal = c->phase_scal + (long)(2 * d + m) * 8;
+      a.nx = R.nx;
+      a.ny = R.ny;
+      a.nz = R.nz;
+      a.ndim = c->ndim;
+      a.n = R.n;
+      a.h = h;
+      a.alpha = pp->alpha_h;
+      a.gamma = pp->gamma;
+      a.dt_ac = dt_ac;
+      a.target = pp->vol_frac[m] * (double)R.n;
+      a.nblocks = phase_blocks(R.n);
+      launch_phase_gmax<T>(a, s);
+      launch_phase_step<T>(a, s);
+      for (int q = 0; q < passes; ++q) launch_phase_pass<T>(a, s);
+      launch_phase_apply<T>(a, s);
+      HIP_TRY(hipGetLastError());
+    }
+  }
+  if (info) {
+    std::vector<double> sc((size_t)c->nprob * 16);
+    HIP_TRY(hipMemcpyAsync(sc.data(), c->phase_scal, sizeof(double) * sc.size(), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (int d = 0; d < c->nprob; ++d) {
+      for (int m = 0; m < 2; ++m) {
+        const double* q = sc.data() + (2 * d + m) * 8;
+        info[d].gmax[m] = m < c->nphase ? q[0] : 0.0;
+        info[d].shift[m] = m < c->nphase ? q[3] : 0.0;
+        info[d].volume[m] = m < c->nphase ? q[4] : 0.0;
+      }
+    }
+  }
+  return PETTO_OK;
+}
+
+}  // namespace
+
+// ====================================================================================== C ABI
+
+extern "C" {
+
+const char* petto_last_error(void) { return g_err.c_str(); }
+
+const char* petto_version(void) { return "petto-mi355x 0.1 (gfx950)"; }
+
+petto_status petto_create(const petto_problem* probs, int32_t nprob, int32_t prec, petto_ctx** out) {
+  g_err.clear();
+  if (out == nullptr) return fail(PETTO_ERR_INVALID, "out is NULL");
+  *out = nullptr;
+  if (probs == nullptr) return fail(PETTO_ERR_INVALID, "probs is NULL");
+  if (nprob < 1 || nprob > kMaxDesigns) return fail(PETTO_ERR_INVALID, "nprob must be in [1, %d]", kMaxDesigns);
+  if (prec != PETTO_FP32 && prec != PETTO_FP64) return fail(PETTO_ERR_INVALID, "prec must be PETTO_FP32 or PETTO_FP64");
+  for (int d = 0; d < nprob; ++d) {
+    PETTO_TRY(validate_problem(probs[d], d));
+    if (probs[d].physics != probs[0].physics || probs[d].ndim != probs[0].ndim || probs[d].nphase != probs[0].nphase)
+      return fail(PETTO_ERR_INVALID, "all designs of a batch need the same physics, ndim and nphase");
+    if (probs[d].physics == PETTO_HEAT) PETTO_TRY(check_heat_mask(probs[d], d));
+  }
+  if (probs[0].physics == PETTO_ELASTIC && nprob != 1)
+    return fail(PETTO_ERR_UNSUPPORTED, "elastic contexts hold one design");
+  if (probs[0].physics == PETTO_HEAT && probs[0].ndim != 2)
+    return fail(PETTO_ERR_UNSUPPORTED, "heat conduction is implemented in 2D");
+
+  petto_ctx* c = new petto_ctx();
+  c->physics = probs[0].physics;
+  c->ndim = probs[0].ndim;
+  c->prec = prec;
+  c->nprob = nprob;
+  c->nphase = probs[0].nphase;
+  c->probs.assign(probs, probs + nprob);
+  // host-side preparation (no GPU yet)
+  std::vector<uint32_t> pin_words;
+  bool any_pin = false;
+  std::vector<double> F;
+  if (c->physics == PETTO_ELASTIC) {
+    petto_status st = prepare_elastic(c, probs[0], pin_words, any_pin, F);
+    if (st < 0) {
+      delete c;
+      return st;
+    }
+    const petto_problem& p = probs[0];
+    c->nstate = padded_state(p);
+    c->ncell = cells(p);
+    c->max_cells = c->ncell;
+    c->state_off = {0, c->nstate};
+    c->cell_off = {0, c->ncell};
+    ElGeom& g = c->geom;
+    g.nx = p.n[0];
+    g.ny = p.n[1];
+    g.nz = p.ndim == 3 ? p.n[2] : 1;
+    g.px = g.nx + 1;
+    g.py = g.ny + 1;
+    g.plane = (long)g.px * g.py * (p.ndim == 3 ? g.nz + 1 : 1);
+    g.h = p.h;
+    g.lam0 = p.nu / ((1.0 + p.nu) * (1.0 - 2.0 * p.nu));
+    g.mu0 = 1.0 / (2.0 * (1.0 + p.nu));
+    for (int s = 0; s < 6; ++s) {
+      const int sd = s < 2 * p.ndim ? p.side[s] : PETTO_SIDE_FREE;
+      g.clamp[s] = sd == PETTO_SIDE_CLAMPED;
+      g.fixn[s] = sd != PETTO_SIDE_FREE;
+    }
+    c->m0 = g.lam0 + 2.0 * g.mu0;
+    c->h_ranges.push_back({0, c->ncell, g.nx, g.ny, g.nz, 0, p.h});
+    c->ntile = c->ndim == 2 ? el2d_tiles(g) : el3d_tiles(g);
+  } else {
+    long soff = 0;
+    int t0 = 0;
+    std::vector<HeatTile> tiles;
+    std::vector<int> tile0;
+    std::vector<uint8_t> dir;
+    F.clear();
+    bool dense = false;
+    for (int d = 0; d < nprob; ++d) dense = dense || probs[d].load != nullptr;
+    for (int d = 0; d < nprob; ++d) {
+      const petto_problem& p = probs[d];
+      const int nx = p.n[0], ny = p.n[1];
+      const long n = (long)nx * ny;
+      HeatDesign hd{};
+      hd.nx = nx;
+      hd.ny = ny;
+      hd.off = soff;
+      hd.tile0 = t0;
+      hd.dir_off = (int)dir.size();
+      hd.h = p.h;
+      hd.fsrc = p.q * p.h * p.h;
+      for (int j = 0; j < ny; ++j) dir.push_back(p.fixed[(long)j * nx] & 1);
+      for (int j = 0; j < ny; ++j) dir.push_back((p.fixed[(long)j * nx + nx - 1] >> 1) & 1);
+      for (int i = 0; i < nx; ++i) dir.push_back((p.fixed[i] >> 2) & 1);
+      for (int i = 0; i < nx; ++i) dir.push_back((p.fixed[(long)(ny - 1) * nx + i] >> 3) & 1);
+      tile0.push_back(t0);
+      for (int j0 = 0; j0 < ny; j0 += 8)
+        for (int i0 = 0; i0 < nx; i0 += 64) tiles.push_back({d, i0, j0, 0});
+      hd.ntile = (int)tiles.size() - t0;
+      t0 = (int)tiles.size();
+      double ss = 0.0;
+      if (dense) {
+        for (long q = 0; q < n; ++q) {
+          const double v = p.load ? p.load[q] : hd.fsrc;
+          if (!is_finite(v)) {
+            delete c;
+            return fail(PETTO_ERR_INVALID, "problem %d: source not finite", d);
+          }
+          F.push_back(v);
+          ss += v * v;
+        }
+      } else {
+        ss = hd.fsrc * hd.fsrc * (double)n;
+      }
+      if (!(ss > 0.0)) {
+        delete c;
+        return fail(PETTO_ERR_INVALID, "problem %d: source is zero", d);
+      }
+      c->fnorm.push_back(std::sqrt(ss));
+      c->h_des.push_back(hd);
+      c->h_ranges.push_back({soff, n, nx, ny, 1, 0, p.h});
+      c->state_off.push_back(soff);
+      c->cell_off.push_back(soff);
+      soff += n;
+      if (n > c->max_cells) c->max_cells = n;
+    }
+    tile0.push_back(t0);
+    c->state_off.push_back(soff);
+    c->cell_off.push_back(soff);
+    c->nstate = soff;
+    c->ncell = soff;
+    c->ntile = t0;
+    c->m0 = 1.0;
+    // device copies
+    auto up = [&]() -> petto_status {
+      PETTO_TRY(upload(c, &c->d_des, c->h_des));
+      PETTO_TRY(upload(c, &c->d_tiles, tiles));
+      PETTO_TRY(upload(c, &c->d_dir, dir));
+      PETTO_TRY(upload(c, &c->d_tile0, tile0));
+      return PETTO_OK;
+    };
+    petto_status st = up();
+    if (st < 0) {
+      petto_destroy(c);
+      return st;
+    }
+  }
+  auto build = [&]() -> petto_status {
+    const size_t es = elem_size(c);
+    if (!F.empty()) {
+      PETTO_TRY(upload(c, &c->F64, F));
+      PETTO_TRY(dalloc(c, &c->Ft, F.size() * es));
+      if (prec == PETTO_FP64) {
+        HIP_TRY(hipMemcpy(c->Ft, F.data(), F.size() * es, hipMemcpyHostToDevice));
+      } else {
+        std::vector<float> f32(F.begin(), F.end());
+        HIP_TRY(hipMemcpy(c->Ft, f32.data(), F.size() * es, hipMemcpyHostToDevice));
+      }
+    }
+    if (any_pin) PETTO_TRY(upload(c, &c->pins, pin_words));
+    c->geom.pins = c->pins;
+    std::vector<long> nc;
+    std::vector<double> hh;
+    for (const auto& r : c->h_ranges) {
+      nc.push_back(r.n);
+      hh.push_back(r.h);
+    }
+    PETTO_TRY(upload(c, &c->d_ranges, c->h_ranges));
+    PETTO_TRY(upload(c, &c->d_ncell, nc));
+    PETTO_TRY(upload(c, &c->d_fnorm, c->fnorm));
+    PETTO_TRY(upload(c, &c->d_h, hh));
+    PETTO_TRY(dalloc(c, &c->ualt, c->nstate * es));
+    PETTO_TRY(dalloc(c, &c->E, c->ncell * es));
+    if (prec == PETTO_FP32) {
+      PETTO_TRY(dalloc_t(c, &c->E64, c->ncell));
+      PETTO_TRY(dalloc_t(c, &c->d32a, c->nstate));
+      PETTO_TRY(dalloc_t(c, &c->d32b, c->nstate));
+      PETTO_TRY(dalloc_t(c, &c->b32, c->nstate));
+    }
+    PETTO_TRY(dalloc_t(c, &c->partial, c->ntile + 64));
+    PETTO_TRY(dalloc_t(c, &c->partial2, c->ntile + 64));
+    PETTO_TRY(dalloc_t(c, &c->partial_max, (size_t)kBpd * nprob));
+    PETTO_TRY(dalloc_t(c, &c->st, nprob));
+    PETTO_TRY(dalloc_t(c, &c->ctl, 4));
+    HIP_TRY(hipMemset(c->ctl, 0, 4 * sizeof(int)));
+    HIP_TRY(hipMemset(c->st, 0, nprob * sizeof(SolveState)));
+    void* ring = nullptr;
+    HIP_TRY(hipHostMalloc(&ring, sizeof(PollRecord) * kRing, hipHostMallocMapped));
+    c->ring_host = static_cast<PollRecord*>(ring);
+    for (int i = 0; i < kRing; ++i) c->ring_host[i] = {0, 0, 0, -1};
+    void* rd = nullptr;
+    HIP_TRY(hipHostGetDevicePointer(&rd, ring, 0));
+    c->ring_dev = static_cast<PollRecord*>(rd);
+    PETTO_TRY(dalloc_t(c, &c->phase_scal, (size_t)nprob * 16));
+    PETTO_TRY(dalloc_t(c, &c->phase_work, c->max_cells));
+    PETTO_TRY(dalloc_t(c, &c->phase_partial, (size_t)phase_blocks(c->max_cells) * (kCand + 1) + 64));
+    PETTO_TRY(dalloc_t(c, &c->comp, (size_t)2 * nprob));
+    return PETTO_OK;
+  };
+  petto_status st = build();
+  if (st < 0) {
+    petto_destroy(c);
+    return st;
+  }
+  *out = c;
+  return PETTO_OK;
+}
+
+petto_status petto_destroy(petto_ctx* ctx) {
+  if (ctx == nullptr) return PETTO_OK;
+  destroy_graphs(ctx);
+  if (ctx->events) {
+    for (int i = 0; i < kRing; ++i) {
+      (void)hipEventDestroy(ctx->ev_end[i]);
+      (void)hipEventDestroy(ctx->ev_beg[i]);
+    }
+  }
+  if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+  for (void* p : ctx->allocations) (void)hipFree(p);
+  if (ctx->ring_host) (void)hipHostFree(ctx->ring_host);
+  delete ctx;
+  return PETTO_OK;
+}
+
+size_t petto_field_offset(const petto_ctx* ctx, int32_t iprob, int32_t field) {
+  if (ctx == nullptr || iprob < 0 || iprob > ctx->nprob) return (size_t)-1;
+  if (field == PETTO_FIELD_STATE) return (size_t)ctx->state_off[iprob];
+  if (field == PETTO_FIELD_CELL) return (size_t)ctx->cell_off[iprob];
+  return (size_t)-1;
+}
+
+petto_status petto_set_timing(petto_ctx* ctx, int32_t on) {
+  if (ctx == nullptr) return fail(PETTO_ERR_INVALID, "ctx is NULL");
+  ctx->timing = on != 0;
+  ctx->timed_ms = 0.0;
+  ctx->timed_sweeps = 0;
+  return PETTO_OK;
+}
+
+double petto_last_sweep_ms(const petto_ctx* ctx, int64_t* sweeps) {
+  if (ctx == nullptr || ctx->timed_sweeps == 0) {
+    if (sweeps) *sweeps = 0;
+    return 0.0;
+  }
+  if (sweeps) *sweeps = ctx->timed_sweeps;
+  return ctx->timed_ms / (double)ctx->timed_sweeps;
+}
+
+petto_status petto_apt_solve(petto_ctx* ctx, const void* phi, void* u, void* v, const petto_apt_params* params,
+                             void* stream, petto_solve_info* info) {
+  g_err.clear();
+  if (ctx == nullptr) return fail(PETTO_ERR_INVALID, "ctx is NULL");
+  if (phi == nullptr || u == nullptr || v == nullptr) return fail(PETTO_ERR_INVALID, "phi, u and v must be non-NULL");
+  PETTO_TRY(check_apt_params(ctx, params));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (ctx->timing) {
+    ctx->timed_ms = 0.0;
+    ctx->timed_sweeps = 0;
+  }
+  if (params->refine) return solve_refine(ctx, phi, u, v, params, s, info);
+  if (ctx->prec == PETTO_FP64) return solve_plain<double>(ctx, phi, u, v, params, s, info);
+  return solve_plain<float>(ctx, phi, u, v, params, s, info);
+}
+
+petto_status petto_residual(petto_ctx* ctx, const void* phi, const void* u, void* r, void* stream) {
+  g_err.clear();
+  if (ctx == nullptr) return fail(PETTO_ERR_INVALID, "ctx is NULL");
+  if (phi == nullptr || u == nullptr || r == nullptr) return fail(PETTO_ERR_INVALID, "phi, u and r must be non-NULL");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  auto run = [&](auto tag) -> petto_status {
+    using T = decltype(tag);
+    PETTO_TRY(material<T>(ctx, phi, s, false));
+    if (ctx->physics == PETTO_ELASTIC) {
+      ElSweep<T> a{};
+      a.uin = static_cast<const T*>(u);
+      a.v = static_cast<T*>(r);
+      a.E = static_cast<const T*>(ctx->E);
+      a.b = static_cast<const T*>(ctx->Ft);
+      if (ctx->ndim == 2) launch_el2d<T, kResid>(ctx->geom, a, s);
+      else launch_el3d<T, kResid>(ctx->geom, a, s);
+    } else {
+      HeatSweep<T> a{};
+      a.uin = static_cast<const T*>(u);
+      a.v = static_cast<T*>(r);
+      a.k = static_cast<const T*>(ctx->E);
+      a.b = static_cast<const T*>(ctx->Ft);
+      a.des = ctx->d_des;
+      a.tiles = ctx->d_tiles;
+      a.dir = ctx->d_dir;
+      a.ntile = ctx->ntile;
+      launch_heat2d<T, kResid>(a, s);
+    }
+    HIP_TRY(hipGetLastError());
+    return PETTO_OK;
+  };
+  if (ctx->prec == PETTO_FP64) return run(double{});
+  return run(float{});
+}
+
+petto_status petto_adjoint(petto_ctx* ctx, const void* phi, const void* u, const void* w, int32_t state_fp64,
+                           void* grad_phi, double* compliance, void* stream) {
+  g_err.clear();
+  if (ctx == nullptr) return fail(PETTO_ERR_INVALID, "ctx is NULL");
+  if (phi == nullptr || u == nullptr || grad_phi == nullptr)
+    return fail(PETTO_ERR_INVALID, "phi, u and grad_phi must be non-NULL");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int nt = 0;
+  if (ctx->prec == PETTO_FP64) {
+    adjoint_launch<double, double>(ctx, phi, u, w, grad_phi, s);
+    nt = ctx->physics == PETTO_HEAT ? ctx->ntile : el_tiles_for(ctx, true);
+  } else if (state_fp64) {
+    adjoint_launch<double, float>(ctx, phi, u, w, grad_phi, s);
+    nt = ctx->physics == PETTO_HEAT ? ctx->ntile : el_tiles_for(ctx, true);
+  } else {
+    adjoint_launch<float, float>(ctx, phi, u, w, grad_phi, s);
+    nt = ctx->physics == PETTO_HEAT ? ctx->ntile : el_tiles_for(ctx, false);
+  }
+  launch_dot_finalize(ctx->partial, ctx->partial2, ctx->physics == PETTO_HEAT ? ctx->d_tile0 : nullptr, nt,
+                      ctx->nprob, compliance ? compliance : ctx->comp, s);
+  HIP_TRY(hipGetLastError());
+  return PETTO_OK;
+}
+
+petto_status petto_phase_update(petto_ctx* ctx, void* phi, const void* grad_phi, const petto_phase_params* pp,
+                                void* stream, petto_phase_info* info) {
+  g_err.clear();
+  if (ctx == nullptr) return fail(PETTO_ERR_INVALID, "ctx is NULL");
+  if (phi == nullptr || grad_phi == nullptr) return fail(PETTO_ERR_INVALID, "phi and grad_phi must be non-NULL");
+  if (pp == nullptr) return fail(PETTO_ERR_INVALID, "phase params are NULL");
+  if (!(pp->alpha_h >= 0.0) || !is_finite(pp->alpha_h)) return fail(PETTO_ERR_INVALID, "alpha_h must be >= 0");
+  if (!(pp->gamma >= 0.0) || !is_finite(pp->gamma)) return fail(PETTO_ERR_INVALID, "gamma must be >= 0");
+  if (!is_finite(pp->dt_ac)) return fail(PETTO_ERR_INVALID, "dt_ac must be finite");
+  double vs = 0.0;
+  for (int m = 0; m < ctx->nphase; ++m) {
+    if (!(pp->vol_frac[m] > 0.0 && pp->vol_frac[m] < 1.0))
+      return fail(PETTO_ERR_INVALID, "vol_frac[%d] must be in (0, 1)", m);
+    vs += pp->vol_frac[m];
+  }
+  if (!(vs < 1.0 || ctx->nphase == 1)) return fail(PETTO_ERR_INVALID, "phase volume fractions must sum below 1");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (ctx->prec == PETTO_FP64) return phase_update_impl<double>(ctx, phi, grad_phi, pp, s, info);
+  return phase_update_impl<float>(ctx, phi, grad_phi, pp, s, info);
+}
+
+petto_status petto_step(petto_ctx* ctx, void* phi, void* u, void* v, void* grad_phi, double* compliance,
+                        const petto_apt_params* ap, const petto_phase_params* pp, void* stream,
+                        petto_solve_info* sinfo, petto_phase_info* pinfo) {
+  g_err.clear();
+  if (ctx == nullptr) return fail(PETTO_ERR_INVALID, "ctx is NULL");
+  if (grad_phi == nullptr) return fail(PETTO_ERR_INVALID, "grad_phi must be non-NULL");
+  if (pp == nullptr) return fail(PETTO_ERR_INVALID, "phase params are NULL");
+  petto_status s1 = petto_apt_solve(ctx, phi, u, v, ap, stream, sinfo);
+  if (s1 < 0) return s1;
+  petto_status s2 = petto_adjoint(ctx, phi, u, nullptr, ap->refine ? 1 : 0, grad_phi, compliance, stream);
+  if (s2 < 0) return s2;
+  petto_status s3 = petto_phase_update(ctx, phi, grad_phi, pp, stream, pinfo);
+  if (s3 < 0) return s3;
+  return s1;
+}
+
+}  // extern "C"

@@ -1,0 +1,217 @@
+// Phase-field design update (Sections 2.4 and 3.1): normalised sensitivity step
+// (Eq. 3.2 weight alpha_h), one explicit Allen-Cahn step with the double-well
+// w = sin^2(pi phi)/64 of Eq. 2.15 and mirror (no-flux) boundaries, and the volume
+// constraint enforced exactly by a uniform shift s: mean(clamp(phi'' + s, 0, ub)) = V.
+//
+// The shift is found by a bracketed 64-way search: each pass evaluates the clamped
+// volume at 63 interior candidates of the current bracket in one sweep over the
+// cells (FP64 sums in a fixed order) and keeps the sub-interval holding the root.
+#include "kernels.hpp"
+
+namespace petto {
+namespace {
+
+constexpr int kMaxPhaseBlocks = 1024;
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void gmax_kernel(PhaseArgs<T> A) {
+  __shared__ double red[kBlock / kWave];
+  double m = 0.0;
+  for (long c = (long)blockIdx.x * kBlock + threadIdx.x; c < A.n; c += (long)gridDim.x * kBlock)
+    m = fmax(m, fabs((double)A.g[c]));
+  m = block_max(m, red);
+  if (threadIdx.x == 0) A.partial[blockIdx.x] = m;
+}
+
+__global__ void gmax_final_kernel(const double* partial, int nb, double* scal) {
+  double m = 0.0;
+  for (int b = threadIdx.x; b < nb; b += kWave) m = fmax(m, partial[b]);
+  m = wave_max(m);
+  if (threadIdx.x == 0) scal[0] = m;
+}
+
+template <typename T>
+__device__ inline double sens_step(const PhaseArgs<T>& A, long c, double gmax) {
+  const double gh = gmax > 0.0 ? (double)A.g[c] / gmax : 0.0;
+  return (double)A.phi[c] - A.alpha * gh;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void step_kernel(PhaseArgs<T> A) {
+  __shared__ double red[kBlock / kWave];
+  const double gmax = A.scal[0];
+  const double rh2 = 1.0 / (A.h * A.h);
+  const double kPi = 3.141592653589793;
+  double mn = INFINITY, mx = -INFINITY, ubmax = (A.prev == nullptr) ? 1.0 : -INFINITY;
+  const long sxy = (long)A.nx * A.ny;
+  for (long c = (long)blockIdx.x * kBlock + threadIdx.x; c < A.n; c += (long)gridDim.x * kBlock) {
+    const int k = (int)(c / sxy);
+    const long rem = c - (long)k * sxy;
+    const int j = (int)(rem / A.nx), i = (int)(rem - (long)j * A.nx);
+    const double x = sens_step(A, c, gmax);
+    // mirror boundaries: a missing neighbour takes the cell's own value
+    const double xl = i > 0 ? sens_step(A, c - 1, gmax) : x;
+    const double xr = i < A.nx - 1 ? sens_step(A, c + 1, gmax) : x;
+    const double yl = j > 0 ? sens_step(A, c - A.nx, gmax) : x;
+    const double yr = j < A.ny - 1 ? sens_step(A, c + A.nx, gmax) : x;
+    double lap = (xl + xr - 2.0 * x) + (yl + yr - 2.0 * x);
+    if (A.ndim == 3) {
+      const double zl = k > 0 ? sens_step(A, c - sxy, gmax) : x;
+      const double zr = k < A.nz - 1 ? sens_step(A, c + sxy, gmax) : x;
+      lap += zl + zr - 2.0 * x;
+    }
+    lap *= rh2;
+    const double wp = (kPi / 64.0) * sin(2.0 * kPi * x);
+    const double y = x - A.dt_ac * (wp - A.gamma * lap);
+    A.work[c] = y;
+    mn = fmin(mn, y);
+    mx = fmax(mx, y);
+    if (A.prev != nullptr) ubmax = fmax(ubmax, 1.0 - (double)A.prev[c]);
+  }
+  const double a = block_min(mn, red);
+  const double b = block_max(mx, red);
+  const double u = block_max(ubmax, red);
+  if (threadIdx.x == 0) {
+    A.partial[3 * blockIdx.x] = a;
+    A.partial[3 * blockIdx.x + 1] = b;
+    A.partial[3 * blockIdx.x + 2] = u;
+  }
+}
+
+// Initial bracket [-max phi'', max ub - min phi''].
+__global__ void bracket_init_kernel(const double* partial, int nb, double* scal, double target) {
+  double mn = INFINITY, mx = -INFINITY, ub = -INFINITY;
+  for (int b = threadIdx.x; b < nb; b += kWave) {
+    mn = fmin(mn, partial[3 * b]);
+    mx = fmax(mx, partial[3 * b + 1]);
+    ub = fmax(ub, partial[3 * b + 2]);
+  }
+  mn = wave_min(mn);
+  mx = wave_max(mx);
+  ub = wave_max(ub);
+  if (threadIdx.x == 0) {
+    scal[1] = -mx;
+    scal[2] = ub - mn;
+    scal[5] = target;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void pass_kernel(PhaseArgs<T> A) {
+  __shared__ double sh[kBlock / kWave][kCand + 1];
+  const double lo = A.scal[1], hi = A.scal[2];
+  const double step = (hi - lo) / (kCand + 1);
+  double acc[kCand];
+#pragma unroll
+  for (int k = 0; k < kCand; ++k) acc[k] = 0.0;
+  for (long c = (long)blockIdx.x * kBlock + threadIdx.x; c < A.n; c += (long)gridDim.x * kBlock) {
+    const double x = A.work[c];
+    const double ub = A.prev == nullptr ? 1.0 : 1.0 - (double)A.prev[c];
+#pragma unroll
+    for (int k = 0; k < kCand; ++k) acc[k] += fmin(fmax(x + (lo + (k + 1) * step), 0.0), ub);
+  }
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+#pragma unroll
+  for (int k = 0; k < kCand; ++k) {
+    const double s = wave_sum(acc[k]);
+    if (lane == 0) sh[w][k] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < kCand) {
+    double s = 0.0;
+    for (int q = 0; q < kBlock / kWave; ++q) s += sh[q][threadIdx.x];
+    A.partial[(long)blockIdx.x * (kCand + 1) + threadIdx.x] = s;
+  }
+}
+
+// Keep the candidate interval holding the root: lo = last candidate with
+// V < target, hi = first candidate with V >= target.
+__global__ void bracket_kernel(const double* partial, int nb, double* scal) {
+  __shared__ double V[kCand];
+  const int k = threadIdx.x;
+  if (k < kCand) {
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b) s += partial[(long)b * (kCand + 1) + k];
+    V[k] = s;
+  }
+  __syncthreads();
+  if (k == 0) {
+    const double lo = scal[1], hi = scal[2], target = scal[5];
+    const double step = (hi - lo) / (kCand + 1);
+    int first = kCand;
+    for (int q = 0; q < kCand; ++q) {
+      if (V[q] >= target) { first = q; break; }
+    }
+    const double nlo = first == 0 ? lo : lo + first * step;
+    const double nhi = first == kCand ? hi : lo + (first + 1) * step;
+    scal[1] = nlo;
+    scal[2] = nhi;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void apply_kernel(PhaseArgs<T> A) {
+  __shared__ double red[kBlock / kWave];
+  const double s = 0.5 * (A.scal[1] + A.scal[2]);
+  double acc = 0.0;
+  for (long c = (long)blockIdx.x * kBlock + threadIdx.x; c < A.n; c += (long)gridDim.x * kBlock) {
+    const double ub = A.prev == nullptr ? 1.0 : 1.0 - (double)A.prev[c];
+    const T y = (T)fmin(fmax(A.work[c] + s, 0.0), ub);
+    A.phi[c] = y;
+    acc += (double)y;
+  }
+  const double t = block_sum(acc, red);
+  if (threadIdx.x == 0) A.partial[blockIdx.x] = t;
+  if (blockIdx.x == 0 && threadIdx.x == 0) A.scal[3] = s;
+}
+
+__global__ void volume_final_kernel(const double* partial, int nb, double* scal, double n) {
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nb; b += kWave) s += partial[b];
+  s = wave_sum(s);
+  if (threadIdx.x == 0) scal[4] = s / n;
+}
+
+}  // namespace
+
+int phase_blocks(long n) {
+  long b = (n + kBlock - 1) / kBlock;
+  if (b > kMaxPhaseBlocks) b = kMaxPhaseBlocks;
+  return b < 1 ? 1 : (int)b;
+}
+
+template <typename T>
+void launch_phase_gmax(const PhaseArgs<T>& a, hipStream_t s) {
+  hipLaunchKernelGGL((gmax_kernel<T>), dim3(a.nblocks), dim3(kBlock), 0, s, a);
+  hipLaunchKernelGGL(gmax_final_kernel, dim3(1), dim3(kWave), 0, s, a.partial, a.nblocks, a.scal);
+}
+
+template <typename T>
+void launch_phase_step(const PhaseArgs<T>& a, hipStream_t s) {
+  hipLaunchKernelGGL((step_kernel<T>), dim3(a.nblocks), dim3(kBlock), 0, s, a);
+  hipLaunchKernelGGL(bracket_init_kernel, dim3(1), dim3(kWave), 0, s, a.partial, a.nblocks, a.scal, a.target);
+}
+
+template <typename T>
+void launch_phase_pass(const PhaseArgs<T>& a, hipStream_t s) {
+  hipLaunchKernelGGL((pass_kernel<T>), dim3(a.nblocks), dim3(kBlock), 0, s, a);
+  hipLaunchKernelGGL(bracket_kernel, dim3(1), dim3(kWave), 0, s, a.partial, a.nblocks, a.scal);
+}
+
+template <typename T>
+void launch_phase_apply(const PhaseArgs<T>& a, hipStream_t s) {
+  hipLaunchKernelGGL((apply_kernel<T>), dim3(a.nblocks), dim3(kBlock), 0, s, a);
+  hipLaunchKernelGGL(volume_final_kernel, dim3(1), dim3(kWave), 0, s, a.partial, a.nblocks, a.scal,
+                     (double)a.n);
+}
+
+template void launch_phase_gmax<float>(const PhaseArgs<float>&, hipStream_t);
+template void launch_phase_gmax<double>(const PhaseArgs<double>&, hipStream_t);
+template void launch_phase_step<float>(const PhaseArgs<float>&, hipStream_t);
+template void launch_phase_step<double>(const PhaseArgs<double>&, hipStream_t);
+template void launch_phase_pass<float>(const PhaseArgs<float>&, hipStream_t);
+template void launch_phase_pass<double>(const PhaseArgs<double>&, hipStream_t);
+template void launch_phase_apply<float>(const PhaseArgs<float>&, hipStream_t);
+template void launch_phase_apply<double>(const PhaseArgs<double>&, hipStream_t);
+
+}  // namespace petto

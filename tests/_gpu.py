@@ -1,0 +1,61 @@
+"""Shared helpers of the GPU parity tests (test code only)."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+
+HAS_GPU = torch.cuda.is_available()
+
+
+def require_gpu():
+    if not HAS_GPU:
+        pytest.skip("no GPU")
+
+
+def announce(msg):
+    """Name the case before a GPU step (flushed, so it survives a lost box)."""
+    print(f"[gpu-case] {msg}", file=sys.stderr, flush=True)
+
+
+def dev(a, dtype):
+    return torch.tensor(np.ascontiguousarray(a).ravel(), dtype=dtype, device="cuda")
+
+
+def host(t, shape=None):
+    a = t.detach().cpu().numpy().astype(np.float64)
+    return a.reshape(shape) if shape is not None else a
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))
+
+
+def context(prob, prec):
+    from paper_2509_06971_amd.api import Context
+    return Context([prob] if not isinstance(prob, list) else prob, prec)
+
+
+def mixed_elastic(ndim):
+    """Ragged grid with clamped, roller and free sides and a few extra pins."""
+    if ndim == 2:
+        n = (150, 37)
+        side = (W.CLAMPED, W.ROLLER, W.FREE, W.CLAMPED, 0, 0)
+    else:
+        n = (70, 9, 7)
+        side = (W.CLAMPED, W.FREE, W.ROLLER, W.CLAMPED, W.CLAMPED, W.FREE)
+    fixed = W._side_normal_fixed(ndim, n, side)
+    valid = W.dof_valid_mask(ndim, n)
+    rng = np.random.default_rng(11)
+    idx = np.argwhere(valid & (fixed == 0))
+    for q in idx[rng.choice(len(idx), 5, replace=False)]:
+        fixed[tuple(q)] = 1
+    load = rng.uniform(-1, 1, fixed.shape)
+    load[~valid] = 0
+    load[fixed.astype(bool)] = 0
+    prob = W.Problem(W.ELASTIC, ndim, n, 1.0 / n[1], 1.0, 1e-3, 0.3, 3.0, side, fixed, load)
+    return prob
