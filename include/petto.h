@@ -206,6 +206,18 @@ double petto_last_sweep_ms(const petto_ctx *ctx, int64_t *sweeps);
 /* Enable (1) or disable (0) the sweep timing above (off by default). */
 petto_status petto_set_timing(petto_ctx *ctx, int32_t on);
 
+/* Sweeps per launch of the 2D elastic relaxation.  k in {2, 4, 5, 8, 10}: each launch
+ * stages an LDS window of the grid and runs k sweeps on it (results bit-identical
+ * to one sweep per launch); k = 1: one sweep per launch; k = 0 (default for FP32
+ * contexts): time the candidates on the first solve and keep the fastest.  A
+ * block of check_every sweeps uses k only when check_every is a multiple of 2k,
+ * else one sweep per launch.  FP64 contexts default to 1.  3D and heat contexts
+ * always use one sweep per launch. */
+petto_status petto_set_blocking(petto_ctx *ctx, int32_t k);
+
+/* The sweeps per launch in use (0: not chosen yet). */
+int32_t petto_blocking(const petto_ctx *ctx);
+
 /* Message of the last failure on the calling thread ("" if none). */
 const char *petto_last_error(void);
 

@@ -93,6 +93,8 @@ def load(path: str = LIB_PATH):
                             C.POINTER(SolveInfo), C.POINTER(PhaseInfo)]),
         "petto_last_sweep_ms": (C.c_double, [vp, C.POINTER(C.c_int64)]),
         "petto_set_timing": (st, [vp, C.c_int32]),
+        "petto_set_blocking": (st, [vp, C.c_int32]),
+        "petto_blocking": (C.c_int32, [vp]),
         "petto_last_error": (C.c_char_p, []),
         "petto_version": (C.c_char_p, []),
     }

@@ -164,6 +164,13 @@ class Context:
         L.check(st)
         return st, [si[i].as_dict() for i in range(self.nprob)], [pi[i].as_dict() for i in range(self.nprob)], comp
 
+    def set_blocking(self, k):
+        """Sweeps per launch of the 2D elastic relaxation (0: autotune)."""
+        L.check(self.lib.petto_set_blocking(self.h, int(k)))
+
+    def blocking(self):
+        return int(self.lib.petto_blocking(self.h))
+
     def set_timing(self, on=True):
         L.check(self.lib.petto_set_timing(self.h, int(bool(on))))
 

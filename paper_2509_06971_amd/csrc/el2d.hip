@@ -9,8 +9,12 @@
 // load = residual r (force units) -> v <- a v + c r, u <- u + dt v (Eqs. 3.9, 3.10,
 // 3.6 and the damped update of Eq. 3.12).  A wavefront owns one 64-wide row, so all
 // global accesses are row-coalesced.
+#include "el2d_ops.hpp"
 #include "kernels.hpp"
 #include "material.hpp"
+
+// Rounding is spelled out in el2d_ops.hpp; keep the compiler from fusing further.
+#pragma clang fp contract(off)
 
 namespace petto {
 namespace {
@@ -115,26 +119,19 @@ __global__ __launch_bounds__(kBlock) void el2d_kernel(ElGeom g, ElSweep<T> A, in
     const T e = sm.E[lj][li];
     const T exx = (sm.ux[lj][li + 1] - sm.ux[lj][li]) * rh;
     const T eyy = (sm.uy[lj + 1][li] - sm.uy[lj][li]) * rh;
-    const T lam = e * lam0, mu = e * mu0;
-    const T tr = exx + eyy;
-    sm.sxx[lj][li] = lam * tr + T(2) * mu * exx;
-    sm.syy[lj][li] = lam * tr + T(2) * mu * eyy;
+    el2d::normal_stress<T>(e * lam0, T(2) * (e * mu0), exx, eyy, sm.sxx[lj][li], sm.syy[lj][li]);
   }
   for (int idx = threadIdx.x; idx < (TY + 1) * (TX + 1); idx += kBlock) {
     const int lj = 1 + idx / (TX + 1), li = 1 + idx % (TX + 1);
     bool on;
     const bool act = vertex_active(g, i0 - 1 + li, j0 - 1 + lj, on);
-    T tau = T(0);
-    if (act) {
-      const T gam = (sm.ux[lj][li] - sm.ux[lj - 1][li]) * rh + (sm.uy[lj][li] - sm.uy[lj][li - 1]) * rh;
-      const T mue = T(0.25) * mu0 *
-                    (sm.E[lj - 1][li - 1] + sm.E[lj - 1][li] + sm.E[lj][li - 1] + sm.E[lj][li]);
-      // On a clamped wall the tangential unknown also drives the reflected ghost:
-      // its coupling to the wall vertex doubles.  Every free unknown a wall vertex
-      // touches is such a reflected tangential one.
-      tau = on ? T(2) * mue * gam : mue * gam;
-    }
-    sm.tau[lj][li] = tau;
+    // On a clamped wall the tangential unknown also drives the reflected ghost, so
+    // its coupling to the wall vertex doubles; every free unknown a wall vertex
+    // touches is such a reflected tangential one.
+    const T mue = el2d::vertex_modulus<T>(mu0, sm.E[lj - 1][li - 1], sm.E[lj - 1][li], sm.E[lj][li - 1],
+                                          sm.E[lj][li], act, on);
+    const T gam = el2d::shear_strain<T>(sm.ux[lj][li], sm.ux[lj - 1][li], sm.uy[lj][li], sm.uy[lj][li - 1], rh);
+    sm.tau[lj][li] = mue * gam;
   }
   __syncthreads();
 
@@ -157,11 +154,12 @@ __global__ __launch_bounds__(kBlock) void el2d_kernel(ElGeom g, ElSweep<T> A, in
       const bool fix = (i == 0 && g.fixn[0]) || (i == nx && g.fixn[1]) || pinned(g.pins, p);
       T rx = T(0);
       if (!fix)
-        rx = bx[r] + h * (sm.sxx[lj][li] - sm.sxx[lj][li - 1]) + h * (sm.tau[lj + 1][li] - sm.tau[lj][li]);
+        rx = el2d::residual<T>(bx[r], h, sm.sxx[lj][li], sm.sxx[lj][li - 1], sm.tau[lj + 1][li], sm.tau[lj][li]);
       if (MODE == kSweep || MODE == kCheck) {
-        const T vn = fix ? vx[r] : ca * vx[r] + cc * rx;
+        T un = sm.ux[lj][li], vn = vx[r];
+        if (!fix) el2d::update<T>(ca, cc, dt, rx, un, vn);
         A.v[p] = vn;
-        A.uout[p] = fix ? sm.ux[lj][li] : sm.ux[lj][li] + dt * vn;
+        A.uout[p] = un;
       } else if (MODE == kResid) {
         A.v[p] = rx;
       } else {
@@ -179,11 +177,12 @@ __global__ __launch_bounds__(kBlock) void el2d_kernel(ElGeom g, ElSweep<T> A, in
       const bool fix = (j == 0 && g.fixn[2]) || (j == ny && g.fixn[3]) || pinned(g.pins, q);
       T ry = T(0);
       if (!fix)
-        ry = by[r] + h * (sm.syy[lj][li] - sm.syy[lj - 1][li]) + h * (sm.tau[lj][li + 1] - sm.tau[lj][li]);
+        ry = el2d::residual<T>(by[r], h, sm.syy[lj][li], sm.syy[lj - 1][li], sm.tau[lj][li + 1], sm.tau[lj][li]);
       if (MODE == kSweep || MODE == kCheck) {
-        const T vn = fix ? vy[r] : ca * vy[r] + cc * ry;
+        T un = sm.uy[lj][li], vn = vy[r];
+        if (!fix) el2d::update<T>(ca, cc, dt, ry, un, vn);
         A.v[q] = vn;
-        A.uout[q] = fix ? sm.uy[lj][li] : sm.uy[lj][li] + dt * vn;
+        A.uout[q] = un;
       } else if (MODE == kResid) {
         A.v[q] = ry;
       } else {

@@ -1,0 +1,222 @@
+// Multi-sweep (temporally blocked) 2D elastic APT kernel for gfx950.
+//
+// A workgroup stages an EX x EY window of grid positions (state, velocity,
+// right-hand side, moduli) once, runs K sweeps on it with the state held in
+// registers and exchanged through LDS, and writes back the inner
+// (EX-2K) x (EY-2K) positions, whose K-step dependency cone lies inside the
+// window.  Each sweep: (B) every position forms its cell's normal stresses and its
+// vertex's shear stress from the LDS state, (C) every unknown takes the stress
+// jumps around it (Eqs. 3.6, 3.9) and the damped update of Eq. 3.12.  The
+// arithmetic is the one of the one-sweep kernel (el2d_ops.hpp), so results are
+// bit-identical for every K.  Per-sweep global traffic drops by about K times.
+#include "el2d_ops.hpp"
+#include "kernels.hpp"
+
+#pragma clang fp contract(off)
+
+namespace petto {
+namespace {
+
+constexpr int EX = 64, EY = 32;          // window of positions
+constexpr int NT = 256;                   // threads: 4 waves, one 64-wide row each
+constexpr int RSTEP = NT / EX;            // rows between a thread's positions
+constexpr int PPT = EY / RSTEP;           // positions per thread
+
+template <typename T>
+struct TbSmem {
+  T dx[EY][EX];
+  T dy[EY][EX];
+  T sxx[EY][EX];                          // cell modulus while staging
+  T syy[EY][EX];
+  T tau[EY][EX];
+  double red[NT / kWave];
+};
+
+__device__ __forceinline__ bool pinned_tb(const uint32_t* pins, long k) {
+  return pins != nullptr && ((pins[k >> 5] >> (k & 31)) & 1u);
+}
+
+template <typename T, int K, bool CHECK>
+__global__ __launch_bounds__(NT) void el2d_tb_kernel(ElGeom g, ElSweep<T> A, int tiles_x, int ntiles) {
+  if (A.st->done) return;
+  static_assert(EX - 2 * K > 0 && EY - 2 * K > 0, "window too small for K sweeps");
+  constexpr int TXI = EX - 2 * K, TYI = EY - 2 * K;
+  __shared__ TbSmem<T> sm;
+  const int tile = xcd_tile(blockIdx.x, ntiles);
+  const int tyi = tile / tiles_x, txi = tile - tyi * tiles_x;
+  const int ie = txi * TXI - K, je = tyi * TYI - K;     // window origin
+  const int li = threadIdx.x % EX, lw = threadIdx.x / EX;
+  const int nx = g.nx, ny = g.ny, px = g.px;
+  const long pl = g.plane;
+  const int i = ie + li;
+
+  T ux[PPT], uy[PPT], vx[PPT], vy[PPT], bx[PPT], by[PPT], lam[PPT], mu2[PPT], mue[PPT];
+  uint32_t freex = 0, freey = 0;
+#pragma unroll
+  for (int s = 0; s < PPT; ++s) {
+    const int lj = lw + s * RSTEP, j = je + lj;
+    const bool validx = i >= 0 && i <= nx && j >= 0 && j < ny;
+    const bool validy = i >= 0 && i < nx && j >= 0 && j <= ny;
+    const long p = (long)j * px + i;
+    ux[s] = vx[s] = bx[s] = uy[s] = vy[s] = by[s] = T(0);
+    if (validx) {
+      ux[s] = A.uin[p];
+      vx[s] = A.v[p];
+      bx[s] = A.b[p];
+      const bool fix = (i == 0 && g.fixn[0]) || (i == nx && g.fixn[1]) || pinned_tb(g.pins, p);
+      if (!fix) freex |= 1u << s;
+    }
+    if (validy) {
+      uy[s] = A.uin[pl + p];
+      vy[s] = A.v[pl + p];
+      by[s] = A.b[pl + p];
+      const bool fix = (j == 0 && g.fixn[2]) || (j == ny && g.fixn[3]) || pinned_tb(g.pins, pl + p);
+      if (!fix) freey |= 1u << s;
+    }
+    const bool cell = i >= 0 && i < nx && j >= 0 && j < ny;
+    sm.sxx[lj][li] = cell ? A.E[(long)j * nx + i] : T(0);
+    sm.dx[lj][li] = ux[s];
+    sm.dy[lj][li] = uy[s];
+  }
+  __syncthreads();
+  const T lam0 = T(g.lam0), mu0 = T(g.mu0);
+#pragma unroll
+  for (int s = 0; s < PPT; ++s) {
+    const int lj = lw + s * RSTEP, j = je + lj;
+    const T e = sm.sxx[lj][li];
+    lam[s] = e * lam0;
+    mu2[s] = T(2) * (e * mu0);
+    // vertex (i, j): active unless on a free/roller side; positions outside the
+    // grid carry no vertex
+    bool act = i >= 0 && j >= 0 && i <= nx && j <= ny, on = false;
+    if (i == 0) { act = act && g.clamp[0]; on = true; }
+    if (i == nx) { act = act && g.clamp[1]; on = true; }
+    if (j == 0) { act = act && g.clamp[2]; on = true; }
+    if (j == ny) { act = act && g.clamp[3]; on = true; }
+    const T e00 = (li > 0 && lj > 0) ? sm.sxx[lj - 1][li - 1] : T(0);
+    const T e10 = lj > 0 ? sm.sxx[lj - 1][li] : T(0);
+    const T e01 = li > 0 ? sm.sxx[lj][li - 1] : T(0);
+    mue[s] = el2d::vertex_modulus<T>(mu0, e00, e10, e01, e, act, on);
+  }
+  __syncthreads();
+
+  const T rh = T(1.0 / g.h), h = T(g.h);
+  const T ca = T(A.st->a), cc = T(A.st->c), dt = T(A.st->dt);
+  const bool cl0 = g.clamp[0], cl1 = g.clamp[1], cl2 = g.clamp[2], cl3 = g.clamp[3];
+  double acc = 0.0;
+  for (int k = 0; k < K; ++k) {
+    // (B) stresses of the cell and the vertex at every position of the window
+#pragma unroll
+    for (int s = 0; s < PPT; ++s) {
+      const int lj = lw + s * RSTEP, j = je + lj;
+      const T uxs = ux[s], uys = uy[s];
+      const T ux_r = li + 1 < EX ? sm.dx[lj][li + 1] : T(0);
+      const T uy_u = lj + 1 < EY ? sm.dy[lj + 1][li] : T(0);
+      const T ux_dn = lj > 0 ? sm.dx[lj - 1][li] : T(0);
+      const T uy_lf = li > 0 ? sm.dy[lj][li - 1] : T(0);
+      // reflected ghosts of clamped sides, as the one-sweep kernel stages them
+      const T ux_below = j == 0 ? (cl2 ? -uxs : T(0)) : ux_dn;
+      const T uy_left = i == 0 ? (cl0 ? -uys : T(0)) : uy_lf;
+      const T ux_here = j == ny ? (cl3 ? -ux_dn : T(0)) : uxs;
+      const T uy_here = i == nx ? (cl1 ? -uy_lf : T(0)) : uys;
+      const T exx = (ux_r - uxs) * rh;
+      const T eyy = (uy_u - uys) * rh;
+      el2d::normal_stress<T>(lam[s], mu2[s], exx, eyy, sm.sxx[lj][li], sm.syy[lj][li]);
+      sm.tau[lj][li] = mue[s] * el2d::shear_strain<T>(ux_here, ux_below, uy_here, uy_left, rh);
+    }
+    __syncthreads();
+    // (C) residuals and the damped update of every free unknown
+#pragma unroll
+    for (int s = 0; s < PPT; ++s) {
+      const int lj = lw + s * RSTEP;
+      const T sxx_l = li > 0 ? sm.sxx[lj][li - 1] : T(0);
+      const T syy_d = lj > 0 ? sm.syy[lj - 1][li] : T(0);
+      const T tau_u = lj + 1 < EY ? sm.tau[lj + 1][li] : T(0);
+      const T tau_r = li + 1 < EX ? sm.tau[lj][li + 1] : T(0);
+      const T t0 = sm.tau[lj][li];
+      const bool inner = CHECK && k == K - 1 && li >= K && li < EX - K && lj >= K && lj < EY - K;
+      if (freex & (1u << s)) {
+        const T rx = el2d::residual<T>(bx[s], h, sm.sxx[lj][li], sxx_l, tau_u, t0);
+        el2d::update<T>(ca, cc, dt, rx, ux[s], vx[s]);
+        if (inner) acc += (double)rx * (double)rx;
+      }
+      if (freey & (1u << s)) {
+        const T ry = el2d::residual<T>(by[s], h, sm.syy[lj][li], syy_d, tau_r, t0);
+        el2d::update<T>(ca, cc, dt, ry, uy[s], vy[s]);
+        if (inner) acc += (double)ry * (double)ry;
+      }
+      sm.dx[lj][li] = ux[s];
+      sm.dy[lj][li] = uy[s];
+    }
+    __syncthreads();
+  }
+  // write back the inner positions (padding slots of the grid get zero)
+#pragma unroll
+  for (int s = 0; s < PPT; ++s) {
+    const int lj = lw + s * RSTEP, j = je + lj;
+    if (li < K || li >= EX - K || lj < K || lj >= EY - K) continue;
+    if (i > nx || j > ny) continue;
+    const long p = (long)j * px + i;
+    if (j < ny) {
+      A.uout[p] = ux[s];
+      A.v[p] = vx[s];
+    } else {
+      A.uout[p] = T(0);
+    }
+    if (i < nx) {
+      A.uout[pl + p] = uy[s];
+      A.v[pl + p] = vy[s];
+    } else {
+      A.uout[pl + p] = T(0);
+    }
+  }
+  if (CHECK) {
+    const double sum = block_sum(acc, sm.red);
+    if (threadIdx.x == 0) A.partial[tile] = sum;
+  }
+}
+
+template <int K>
+void tb_tiles(const ElGeom& g, int& tx, int& ty) {
+  tx = (g.nx + 1 + (EX - 2 * K) - 1) / (EX - 2 * K);
+  ty = (g.ny + 1 + (EY - 2 * K) - 1) / (EY - 2 * K);
+}
+
+}  // namespace
+
+int el2d_tb_tiles(const ElGeom& g, int K) {
+  int tx = 0, ty = 0;
+  switch (K) {
+    case 2: tb_tiles<2>(g, tx, ty); break;
+    case 4: tb_tiles<4>(g, tx, ty); break;
+    case 5: tb_tiles<5>(g, tx, ty); break;
+    case 8: tb_tiles<8>(g, tx, ty); break;
+    case 10: tb_tiles<10>(g, tx, ty); break;
+    default: return 0;
+  }
+  return tx * ty;
+}
+
+template <typename T, int K, bool CHECK>
+int launch_el2d_tb(const ElGeom& g, const ElSweep<T>& a, hipStream_t s) {
+  int tx, ty;
+  tb_tiles<K>(g, tx, ty);
+  const int nt = tx * ty;
+  hipLaunchKernelGGL((el2d_tb_kernel<T, K, CHECK>), dim3(nt), dim3(NT), 0, s, g, a, tx, nt);
+  return nt;
+}
+
+#define PETTO_TB(T, K)                                                                 \
+  template int launch_el2d_tb<T, K, false>(const ElGeom&, const ElSweep<T>&, hipStream_t); \
+  template int launch_el2d_tb<T, K, true>(const ElGeom&, const ElSweep<T>&, hipStream_t);
+PETTO_TB(float, 2)
+PETTO_TB(float, 4)
+PETTO_TB(float, 5)
+PETTO_TB(float, 8)
+PETTO_TB(float, 10)
+PETTO_TB(double, 2)
+PETTO_TB(double, 4)
+PETTO_TB(double, 5)
+#undef PETTO_TB
+
+}  // namespace petto

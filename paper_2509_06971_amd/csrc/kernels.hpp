@@ -37,6 +37,11 @@ template <typename T, int MODE>
 int launch_el3d(const ElGeom& g, const ElSweep<T>& a, hipStream_t s);
 int el2d_tiles(const ElGeom& g);
 int el3d_tiles(const ElGeom& g);   // the larger tile count of the two precisions
+// K sweeps per launch on an LDS window (K in {2, 4, 5, 8, 10}); bit-identical to K
+// launches of the one-sweep kernel.  CHECK: the last sweep also sums r^2.
+template <typename T, int K, bool CHECK>
+int launch_el2d_tb(const ElGeom& g, const ElSweep<T>& a, hipStream_t s);
+int el2d_tb_tiles(const ElGeom& g, int K);   // 0 for an unsupported K
 int el3d_tiles_prec(const ElGeom& g, bool fp64);
 
 // Sensitivity: per cell g = -dE/dphi * B(w,u)/E-free form, plus dot(F,u) and 2 Pi(u)

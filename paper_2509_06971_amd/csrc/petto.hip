@@ -9,7 +9,9 @@
 #include <cstdio>
 #include <cstring>
 #include <functional>
+#include <type_traits>
 #include <string>
+#include <algorithm>
 #include <vector>
 
 #include "kernels.hpp"
@@ -102,6 +104,7 @@ struct petto_ctx {
   hipEvent_t ev_beg[kRing] = {};
   bool events = false;
   std::vector<GraphEntry> graphs;
+  int blocking = 0;                    // sweeps per launch (2D elastic); 0: tune on first solve
   bool timing = false;
   double timed_ms = 0.0;
   int64_t timed_sweeps = 0;
@@ -367,29 +370,73 @@ petto_status check_apt_params(const petto_ctx* c, const petto_apt_params* p) {
 
 // ------------------------------------------------------------------------------ sweep bodies
 
-// nchk sweeps ping-ponging u <-> ualt (nchk even: the result lands in u).  With
-// `check`, the last one also sums r^2 for the finalize kernel.
+// Sweeps per launch for a block of nchk sweeps: the context's choice when the
+// block splits into an even number of launches of that size, else 1.
+int block_k(const petto_ctx* c, int nchk) {
+  if (c->physics != PETTO_ELASTIC || c->ndim != 2) return 1;
+  const int k = c->blocking > 0 ? c->blocking : 1;
+  return (k > 1 && nchk % (2 * k) == 0) ? k : 1;
+}
+
+template <typename T, bool CHECK>
+int launch_tb(int k, const ElGeom& g, const ElSweep<T>& a, hipStream_t s) {
+  switch (k) {
+    case 2: return launch_el2d_tb<T, 2, CHECK>(g, a, s);
+    case 4: return launch_el2d_tb<T, 4, CHECK>(g, a, s);
+    case 5: return launch_el2d_tb<T, 5, CHECK>(g, a, s);
+    case 8: return launch_el2d_tb<T, 8, CHECK>(g, a, s);
+    case 10: return launch_el2d_tb<T, 10, CHECK>(g, a, s);
+    default: return 0;
+  }
+}
+
+template <>
+int launch_tb<double, false>(int k, const ElGeom& g, const ElSweep<double>& a, hipStream_t s) {
+  switch (k) {
+    case 2: return launch_el2d_tb<double, 2, false>(g, a, s);
+    case 4: return launch_el2d_tb<double, 4, false>(g, a, s);
+    case 5: return launch_el2d_tb<double, 5, false>(g, a, s);
+    default: return 0;
+  }
+}
+
+template <>
+int launch_tb<double, true>(int k, const ElGeom& g, const ElSweep<double>& a, hipStream_t s) {
+  switch (k) {
+    case 2: return launch_el2d_tb<double, 2, true>(g, a, s);
+    case 4: return launch_el2d_tb<double, 4, true>(g, a, s);
+    case 5: return launch_el2d_tb<double, 5, true>(g, a, s);
+    default: return 0;
+  }
+}
+
+// nchk sweeps ping-ponging u <-> ualt (an even number of launches: the result
+// lands in u).  With `check`, the last sweep also sums r^2 for the finalize
+// kernel.  Returns the number of partial-sum slots the check launch writes.
 template <typename T>
-void elastic_sweeps(const petto_ctx* c, hipStream_t s, T* u, T* ualt, T* v, const T* E, const T* b,
-                    SolveState* st, int nchk, bool check = false) {
+int elastic_sweeps(const petto_ctx* c, hipStream_t s, T* u, T* ualt, T* v, const T* E, const T* b,
+                   SolveState* st, int nchk, bool check = false) {
   ElSweep<T> a{};
   a.v = v;
   a.E = E;
   a.b = b;
   a.st = st;
   a.partial = c->partial;
-  for (int q = 0; q < nchk; ++q) {
+  const int k = block_k(c, nchk);
+  const int nl = nchk / k;
+  int nt = 0;
+  for (int q = 0; q < nl; ++q) {
     a.uin = (q & 1) ? ualt : u;
     a.uout = (q & 1) ? u : ualt;
-    const bool chk = check && q == nchk - 1;
+    const bool chk = check && q == nl - 1;
     if (c->ndim == 2) {
-      if (chk) launch_el2d<T, kCheck>(c->geom, a, s);
-      else launch_el2d<T, kSweep>(c->geom, a, s);
+      if (k > 1) nt = chk ? launch_tb<T, true>(k, c->geom, a, s) : launch_tb<T, false>(k, c->geom, a, s);
+      else nt = chk ? launch_el2d<T, kCheck>(c->geom, a, s) : launch_el2d<T, kSweep>(c->geom, a, s);
     } else {
-      if (chk) launch_el3d<T, kCheck>(c->geom, a, s);
-      else launch_el3d<T, kSweep>(c->geom, a, s);
+      nt = chk ? launch_el3d<T, kCheck>(c->geom, a, s) : launch_el3d<T, kSweep>(c->geom, a, s);
     }
   }
+  return nt;
 }
 
 template <typename T>
@@ -419,12 +466,13 @@ int el_tiles_for(const petto_ctx* c, bool fp64) {
   return el3d_tiles_prec(c->geom, fp64);   // 3D tiles depend on the kernel precision
 }
 
-void finalize(const petto_ctx* c, hipStream_t s, SolveState* st, bool fp64_tiles, int mode) {
+// ntile: partial-sum slots the checking launch wrote (elastic; heat uses its list).
+void finalize(const petto_ctx* c, hipStream_t s, SolveState* st, int ntile, int mode) {
   FinalizeArgs f{};
   f.st = st;
   f.partial = c->partial;
   f.tile0 = c->physics == PETTO_HEAT ? c->d_tile0 : nullptr;
-  f.ntile = c->physics == PETTO_HEAT ? c->ntile : el_tiles_for(c, fp64_tiles);
+  f.ntile = c->physics == PETTO_HEAT ? c->ntile : ntile;
   f.ndes = c->nprob;
   f.ncell = c->d_ncell;
   f.ctl = c->ctl;
@@ -483,6 +531,61 @@ petto_status status_of(const std::vector<SolveState>& h) {
   return worst;
 }
 
+// Sweeps-per-launch autotuner (2D elastic, FP32): after setup has written the
+// sweep coefficients, time each candidate on workspace buffers (the caller's
+// state is untouched) and keep the fastest per swept cell.  Results do not depend
+// on the choice (all candidates are bit-identical).
+petto_status ensure_blocking(petto_ctx* c, hipStream_t s, int nchk) {
+  if (c->blocking != 0) return PETTO_OK;
+  if (c->physics != PETTO_ELASTIC || c->ndim != 2 || c->prec != PETTO_FP32) {
+    c->blocking = 1;
+    return PETTO_OK;
+  }
+  PETTO_TRY(ensure_events(c));
+  float* u = c->d32a;
+  float* ua = c->d32b;
+  float* v = static_cast<float*>(c->ualt);
+  launch_fill<float>(u, c->nstate, 0.f, s);
+  launch_fill<float>(v, c->nstate, 0.f, s);
+  ElSweep<float> a{};
+  a.v = v;
+  a.E = static_cast<const float*>(c->E);
+  a.b = c->b32;
+  a.st = c->st;
+  a.partial = c->partial;
+  launch_fill<float>(c->b32, c->nstate, 0.f, s);
+  const int cand[] = {1, 2, 4, 5, 8, 10};
+  double best = 1e300;
+  int best_k = 1;
+  for (int k : cand) {
+    if (nchk % (2 * k) != 0) continue;
+    const int reps = 40 / k < 4 ? 4 : 40 / k;
+    auto run = [&](int n) {
+      for (int q = 0; q < n; ++q) {
+        a.uin = (q & 1) ? ua : u;
+        a.uout = (q & 1) ? u : ua;
+        if (k == 1) launch_el2d<float, kSweep>(c->geom, a, s);
+        else launch_tb<float, false>(k, c->geom, a, s);
+      }
+    };
+    run(2);
+    HIP_TRY(hipEventRecord(c->ev_beg[0], s));
+    run(reps);
+    HIP_TRY(hipEventRecord(c->ev_end[0], s));
+    HIP_TRY(hipEventSynchronize(c->ev_end[0]));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, c->ev_beg[0], c->ev_end[0]));
+    const double per_sweep = ms / (double)(reps * k);
+    if (per_sweep < best) {
+      best = per_sweep;
+      best_k = k;
+    }
+  }
+  HIP_TRY(hipGetLastError());
+  c->blocking = best_k;
+  return PETTO_OK;
+}
+
 // Plain relaxation in the context precision.
 template <typename T>
 petto_status solve_plain(petto_ctx* c, const void* phi, void* u, void* v, const petto_apt_params* ap,
@@ -498,13 +601,15 @@ petto_status solve_plain(petto_ctx* c, const void* phi, void* u, void* v, const 
   const T* E = static_cast<const T*>(c->E);
   const T* b = static_cast<const T*>(c->Ft);
   const int nchk = ap->check_every;
+  if (std::is_same<T, float>::value) PETTO_TRY(ensure_blocking(c, s, nchk));
   std::function<void(hipStream_t)> body = [=](hipStream_t st) {
-    if (c->physics == PETTO_ELASTIC) elastic_sweeps<T>(c, st, uu, ua, vv, E, b, c->st, nchk, true);
+    int nt = 0;
+    if (c->physics == PETTO_ELASTIC) nt = elastic_sweeps<T>(c, st, uu, ua, vv, E, b, c->st, nchk, true);
     else heat_sweeps<T>(c, st, uu, ua, vv, E, b, c->st, nchk, true);
-    finalize(c, st, c->st, sizeof(T) == 8, 0);
+    finalize(c, st, c->st, nt, 0);
   };
   std::vector<const void*> key = {uu, ua, vv, E, b, (const void*)(long)nchk, (const void*)(long)sizeof(T),
-                                  (const void*)1};
+                                  (const void*)1, (const void*)(long)block_k(c, nchk)};
   PollRecord last{};
   PETTO_TRY(run_blocks(c, s, ap->use_graph != 0, key, body, nchk, &last));
   std::vector<SolveState> h;
@@ -531,6 +636,7 @@ petto_status solve_refine(petto_ctx* c, const void* phi, void* u, void* v, const
                           hipStream_t s, petto_solve_info* info) {
   PETTO_TRY(material<float>(c, phi, s, true));
   PETTO_TRY(setup(c, s, c->st, ap, ap->tol, 0, ap->max_iter));
+  PETTO_TRY(ensure_blocking(c, s, ap->check_every));
   double* u64 = static_cast<double*>(u);
   float* v32 = static_cast<float*>(v);
   float* da = c->d32a;
@@ -568,11 +674,12 @@ petto_status solve_refine(petto_ctx* c, const void* phi, void* u, void* v, const
       a.ntile = c->ntile;
       launch_heat2d<double, kRefine>(a, st);
     }
-    finalize(c, st, c->st, true, 1);
+    finalize(c, st, c->st, c->physics == PETTO_ELASTIC ? el_tiles_for(c, true) : 0, 1);
     if (c->physics == PETTO_ELASTIC) elastic_sweeps<float>(c, st, da, db, v32, E, b, c->st, nchk);
     else heat_sweeps<float>(c, st, da, db, v32, E, b, c->st, nchk);
   };
-  std::vector<const void*> key = {u64, da, db, v32, E, b, (const void*)(long)nchk, (const void*)2};
+  std::vector<const void*> key = {u64, da, db, v32, E, b, (const void*)(long)nchk, (const void*)2,
+                                  (const void*)(long)block_k(c, nchk)};
   PollRecord last{};
   PETTO_TRY(run_blocks(c, s, ap->use_graph != 0, key, body, nchk, &last));
   std::vector<SolveState> h;
@@ -755,6 +862,8 @@ petto_status petto_create(const petto_problem* probs, int32_t nprob, int32_t pre
     c->m0 = g.lam0 + 2.0 * g.mu0;
     c->h_ranges.push_back({0, c->ncell, g.nx, g.ny, g.nz, 0, p.h});
     c->ntile = c->ndim == 2 ? el2d_tiles(g) : el3d_tiles(g);
+    if (c->ndim == 2)
+      for (int k : {2, 4, 5, 8, 10}) c->ntile = std::max(c->ntile, el2d_tb_tiles(g, k));
   } else {
     long soff = 0;
     int t0 = 0;
@@ -889,6 +998,7 @@ petto_status petto_create(const petto_problem* probs, int32_t nprob, int32_t pre
     petto_destroy(c);
     return st;
   }
+  c->blocking = prec == PETTO_FP64 ? 1 : 0;
   *out = c;
   return PETTO_OK;
 }
@@ -932,6 +1042,19 @@ double petto_last_sweep_ms(const petto_ctx* ctx, int64_t* sweeps) {
   if (sweeps) *sweeps = ctx->timed_sweeps;
   return ctx->timed_ms / (double)ctx->timed_sweeps;
 }
+
+petto_status petto_set_blocking(petto_ctx* ctx, int32_t k) {
+  g_err.clear();
+  if (ctx == nullptr) return fail(PETTO_ERR_INVALID, "ctx is NULL");
+  const bool ok = k == 0 || k == 1 || k == 2 || k == 4 || k == 5 || (ctx->prec == PETTO_FP32 && (k == 8 || k == 10));
+  if (!ok) return fail(PETTO_ERR_INVALID, "unsupported sweeps per launch %d", k);
+  if (k == 0 && ctx->prec == PETTO_FP64) k = 1;
+  ctx->blocking = k;
+  destroy_graphs(ctx);
+  return PETTO_OK;
+}
+
+int32_t petto_blocking(const petto_ctx* ctx) { return ctx ? ctx->blocking : 0; }
 
 petto_status petto_apt_solve(petto_ctx* ctx, const void* phi, void* u, void* v, const petto_apt_params* params,
                              void* stream, petto_solve_info* info) {

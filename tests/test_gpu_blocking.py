@@ -1,0 +1,63 @@
+"""Multi-sweep launches are bit-identical to one sweep per launch, and agree with
+the oracle; the autotuner's choice is one of the supported values."""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import design
+from _gpu import announce, context, dev, host, mixed_elastic, rel_l2, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("prec,ks", [("fp32", (1, 2, 4, 5, 8, 10)), ("fp64", (1, 2, 4, 5))])
+@pytest.mark.parametrize("name", ["mixed2d", "cant2d_ragged"])
+def test_blocking_bit_identical(name, prec, ks):
+    require_gpu()
+    prob = mixed_elastic(2) if name == "mixed2d" else W.cantilever2d(203, 61)
+    announce(f"blocking {name} {prec} ks={ks}")
+    phi = W.random_phi(prob, 6, 0.2, 1.0)
+    u0 = W.random_u(prob, 7, scale=1e-2)
+    dtype = torch.float64 if prec == "fp64" else torch.float32
+    if prec == "fp32":
+        phi = phi.astype(np.float32).astype(np.float64)
+        u0 = u0.astype(np.float32).astype(np.float64)
+    ctx = context(prob, prec)
+    outs = {}
+    for k in ks:
+        ctx.set_blocking(k)
+        u = dev(u0, dtype)
+        v = ctx.new_state()
+        st, info = ctx.solve(dev(phi, dtype), u, v, theta=1.0, replay_iters=400, check_every=80)
+        assert info[0]["iters"] == 400
+        outs[k] = (u.cpu().numpy().copy(), v.cpu().numpy().copy(), info[0]["rel_res"])
+    ref = outs[ks[0]]
+    for k in ks[1:]:
+        assert np.array_equal(outs[k][0], ref[0]), k
+        assert np.array_equal(outs[k][1], ref[1]), k
+        # the norm is summed per tile, and the tiling differs: equal up to summation order
+        assert outs[k][2] == pytest.approx(ref[2], rel=1e-12), k
+    res, _ = design.solve(phi, prob, u0=u0, params=design.AptParams(theta=1.0, check_every=80), n_iter=400)
+    assert rel_l2(ref[0].reshape(prob.u_shape()), res.u) < (1e-12 if prec == "fp64" else 2e-5)
+    ctx.close()
+
+
+def test_refined_solve_same_for_every_blocking_and_autotune():
+    require_gpu()
+    prob = W.cantilever2d(128, 64)
+    announce("refined solve, blocking and autotune")
+    phi = dev(W.random_phi(prob, 3, 0.3, 1.0), torch.float32)
+    ctx = context(prob, "fp32")
+    outs = []
+    for k in (1, 5, 0):
+        ctx.set_blocking(k)
+        u = ctx.new_state(torch.float64)
+        v = ctx.new_state()
+        st, info = ctx.solve(phi, u, v, theta=4.0, tol=1e-7, refine=True, check_every=100)
+        outs.append((u.cpu().numpy(), info[0]["iters"]))
+    assert ctx.blocking() in (1, 2, 5, 10)
+    for u, it in outs[1:]:
+        assert it == outs[0][1]
+        assert np.array_equal(u, outs[0][0])
+    ctx.close()
