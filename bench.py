@@ -44,6 +44,13 @@ def parse():
     ap.add_argument("--cpu-sweeps", type=int, default=100)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-timing", action="store_true", help="skip the library's sweep-block events")
+    ap.add_argument("--workload", default="cantilever2d",
+                    help="cantilever2d (design steps, the default line) or, for sweep throughput only: "
+                         "heat_batch64, cantilever3d_128x64x64, multimaterial3d_256x128x128")
+    ap.add_argument("--sweeps", type=int, default=2000, help="sweep-throughput legs: sweeps to time")
+    ap.add_argument("--ttd-steps", type=int, default=0,
+                    help="time to converged design: run this many design steps in FP32 (refined, graphs, "
+                         "multi-sweep launches) and in FP64 (one sweep per launch, no graphs)")
     return ap.parse_args()
 
 
@@ -66,12 +73,117 @@ def cpu_baseline(prob, phi0, sweeps):
                       f"{prob.n[0]}x{prob.n[1]} grid (FP64 NumPy/SciPy, single-threaded sparse products)"}
 
 
+# Algorithmic bytes per cell and sweep of the other FP32 sweep kernels (state and
+# velocity read + written, material read; the heat batch has a uniform source).
+BYTES_PER_CELL = {"heat_batch64": 20, "cantilever3d_128x64x64": 52, "multimaterial3d_256x128x128": 52}
+
+
+def sweep_leg(args):
+    """Sweep throughput of one FP32 kernel family at a configuration's full size:
+    a fixed number of sweeps from rest (plain FP32, no refinement) timed with the
+    library's block events and with the wall clock."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2509_06971_amd.api import Context
+    from paper_2509_06971_amd.profile_run import make
+
+    probs = make(args.workload)
+    ctx = Context(probs, "fp32")
+    if len(probs) == 1:
+        phi = W.random_phi(probs[0], 1, 0.05, 1.0).ravel()
+    else:
+        phi = np.concatenate([W.random_phi(p, d, 0.0, 1.0).ravel() for d, p in enumerate(probs)])
+    phi_t = torch.tensor(phi, dtype=torch.float32, device="cuda")
+    u = ctx.new_state()
+    v = ctx.new_state()
+    ncell = sum(p.ncell for p in probs)
+    ctx.solve(phi_t, u, v, theta=1.0, replay_iters=200, check_every=100)   # warm-up
+    ctx.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st, info = ctx.solve(phi_t, u, v, theta=1.0, replay_iters=args.sweeps, check_every=100)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms, n = ctx.last_sweep_ms()
+    bpc = BYTES_PER_CELL[args.workload]
+    achieved = bpc * ncell / (ms * 1e-3) / 1e9
+    out = {"metric": "APT cell-updates/s (sweep throughput)", "value": ncell * args.sweeps / wall,
+           "unit": "cell-updates/s", "n_gpus": 1, "steps": args.sweeps, "warmup": 200,
+           "ms_per_step": 1000.0 * wall / args.sweeps, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": args.workload, "cells": ncell, "designs": len(probs)},
+           "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": achieved / HBM_PEAK_GBS, "traffic": None, "sweep_us": ms * 1e3,
+                        "bytes_per_cell": bpc}}
+    ctx.close()
+    print(json.dumps(out))
+
+
+def ttd_leg(args):
+    """Time to converged design on the 2D cantilever: the same number of design
+    steps (each relaxed to rho <= tol) in the FP32 production mode and in the FP64
+    plain mode, from the same start."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2509_06971_amd.api import Context
+
+    prob = W.cantilever2d(args.nx, args.ny)
+    phi0 = W.initial_phi(prob)
+    res = {}
+    for mode in ("fp32", "fp64"):
+        ctx = Context(prob, mode)
+        if mode == "fp64":
+            ctx.set_blocking(1)
+        dtype = torch.float32 if mode == "fp32" else torch.float64
+        phi = torch.tensor(phi0.ravel(), dtype=dtype, device="cuda")
+        u = ctx.new_state(torch.float64)
+        v = ctx.new_state()
+        g = ctx.new_cells()
+        comp = torch.zeros(2, dtype=torch.float64, device="cuda")
+        apt = dict(theta=args.theta, tol=args.tol, check_every=100, refine=(mode == "fp32"),
+                   use_graph=(mode == "fp32"))
+        sweeps, hist = 0, []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s in range(args.ttd_steps):
+            st, si, pi, _ = ctx.step(phi, u, v, g, vol_frac=prob.vol_frac, compliance=comp, apt=apt)
+            sweeps += si[0]["iters"]
+            hist.append(si[0]["iters"])
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        res[mode] = {"seconds": wall, "sweeps": sweeps, "compliance": comp[0].item(),
+                     "energy2": comp[1].item(), "sweeps_per_step": hist,
+                     "phi_final": phi.double().cpu().numpy()}
+        ctx.close()
+    d_phi = float(np.abs(res["fp32"]["phi_final"] - res["fp64"]["phi_final"]).max())
+    for m in res:
+        res[m].pop("phi_final")
+    out = {"metric": "time to converged design FP32 vs FP64", "config": {
+        "workload": f"cantilever2d_{args.nx}x{args.ny}", "design_steps": args.ttd_steps, "tol": args.tol,
+        "theta": args.theta},
+        "fp32_refined_graph": res["fp32"], "fp64_plain": res["fp64"],
+        "speedup": res["fp64"]["seconds"] / res["fp32"]["seconds"],
+        "rel_compliance_diff": abs(res["fp32"]["compliance"] - res["fp64"]["compliance"]) /
+        res["fp64"]["compliance"], "max_design_diff": d_phi}
+    print(json.dumps(out))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
                                    "(multi-GPU sharding is described in DESIGN.md, not implemented)"}))
         sys.exit(2)
+    if args.ttd_steps > 0:
+        ttd_leg(args)
+        return
+    if args.workload != "cantilever2d":
+        sweep_leg(args)
+        return
     import numpy as np
     import torch
 
