@@ -18,17 +18,18 @@ namespace petto {
 namespace {
 
 constexpr int EX = 64, EY = 32;          // window of positions
-constexpr int NT = 256;                   // threads: 4 waves, one 64-wide row each
+constexpr int NT = 512;                   // threads: 8 waves, one 64-wide row each
 constexpr int RSTEP = NT / EX;            // rows between a thread's positions
 constexpr int PPT = EY / RSTEP;           // positions per thread
+constexpr int PX = EX + 2, PY = EY + 2;   // LDS arrays carry a one-position pad ring
 
 template <typename T>
 struct TbSmem {
-  T dx[EY][EX];
-  T dy[EY][EX];
-  T sxx[EY][EX];                          // cell modulus while staging
-  T syy[EY][EX];
-  T tau[EY][EX];
+  T dx[PY][PX];
+  T dy[PY][PX];
+  T sxx[PY][PX];                          // cell modulus while staging
+  T syy[PY][PX];
+  T tau[PY][PX];
   double red[NT / kWave];
 };
 
@@ -36,6 +37,9 @@ __device__ __forceinline__ bool pinned_tb(const uint32_t* pins, long k) {
   return pins != nullptr && ((pins[k >> 5] >> (k & 31)) & 1u);
 }
 
+// Window position (li, lj) lives at LDS [lj + 1][li + 1]; the pad ring stays zero,
+// so neighbour reads need no guards (edge results are outside the written inner
+// region anyway).
 template <typename T, int K, bool CHECK>
 __global__ __launch_bounds__(NT) void el2d_tb_kernel(ElGeom g, ElSweep<T> A, int tiles_x, int ntiles) {
   if (A.st->done) return;
@@ -49,9 +53,22 @@ __global__ __launch_bounds__(NT) void el2d_tb_kernel(ElGeom g, ElSweep<T> A, int
   const int nx = g.nx, ny = g.ny, px = g.px;
   const long pl = g.plane;
   const int i = ie + li;
+  const int c = li + 1;                                  // LDS column
+
+  // zero the pad ring (rows 0 and PY-1, columns 0 and PX-1) of every array
+  for (int q = threadIdx.x; q < 2 * PX + 2 * EY; q += NT) {
+    int r, cc;
+    if (q < 2 * PX) { r = q < PX ? 0 : PY - 1; cc = q % PX; }
+    else { const int t = q - 2 * PX; r = 1 + t / 2; cc = (t & 1) ? PX - 1 : 0; }
+    sm.dx[r][cc] = T(0);
+    sm.dy[r][cc] = T(0);
+    sm.sxx[r][cc] = T(0);
+    sm.syy[r][cc] = T(0);
+    sm.tau[r][cc] = T(0);
+  }
 
   T ux[PPT], uy[PPT], vx[PPT], vy[PPT], bx[PPT], by[PPT], lam[PPT], mu2[PPT], mue[PPT];
-  uint32_t freex = 0, freey = 0;
+  T fx[PPT], fy[PPT];                       // 1 for a free unknown, 0 otherwise
 #pragma unroll
   for (int s = 0; s < PPT; ++s) {
     const int lj = lw + s * RSTEP, j = je + lj;
@@ -59,94 +76,94 @@ __global__ __launch_bounds__(NT) void el2d_tb_kernel(ElGeom g, ElSweep<T> A, int
     const bool validy = i >= 0 && i < nx && j >= 0 && j <= ny;
     const long p = (long)j * px + i;
     ux[s] = vx[s] = bx[s] = uy[s] = vy[s] = by[s] = T(0);
+    fx[s] = fy[s] = T(0);
     if (validx) {
       ux[s] = A.uin[p];
       vx[s] = A.v[p];
       bx[s] = A.b[p];
       const bool fix = (i == 0 && g.fixn[0]) || (i == nx && g.fixn[1]) || pinned_tb(g.pins, p);
-      if (!fix) freex |= 1u << s;
+      fx[s] = fix ? T(0) : T(1);
     }
     if (validy) {
       uy[s] = A.uin[pl + p];
       vy[s] = A.v[pl + p];
       by[s] = A.b[pl + p];
       const bool fix = (j == 0 && g.fixn[2]) || (j == ny && g.fixn[3]) || pinned_tb(g.pins, pl + p);
-      if (!fix) freey |= 1u << s;
+      fy[s] = fix ? T(0) : T(1);
     }
     const bool cell = i >= 0 && i < nx && j >= 0 && j < ny;
-    sm.sxx[lj][li] = cell ? A.E[(long)j * nx + i] : T(0);
-    sm.dx[lj][li] = ux[s];
-    sm.dy[lj][li] = uy[s];
+    sm.sxx[lj + 1][c] = cell ? A.E[(long)j * nx + i] : T(0);
+    sm.dx[lj + 1][c] = ux[s];
+    sm.dy[lj + 1][c] = uy[s];
   }
   __syncthreads();
   const T lam0 = T(g.lam0), mu0 = T(g.mu0);
 #pragma unroll
   for (int s = 0; s < PPT; ++s) {
-    const int lj = lw + s * RSTEP, j = je + lj;
-    const T e = sm.sxx[lj][li];
+    const int lj = lw + s * RSTEP, j = je + lj, r = lj + 1;
+    const T e = sm.sxx[r][c];
     lam[s] = e * lam0;
     mu2[s] = T(2) * (e * mu0);
-    // vertex (i, j): active unless on a free/roller side; positions outside the
-    // grid carry no vertex
     bool act = i >= 0 && j >= 0 && i <= nx && j <= ny, on = false;
     if (i == 0) { act = act && g.clamp[0]; on = true; }
     if (i == nx) { act = act && g.clamp[1]; on = true; }
     if (j == 0) { act = act && g.clamp[2]; on = true; }
     if (j == ny) { act = act && g.clamp[3]; on = true; }
-    const T e00 = (li > 0 && lj > 0) ? sm.sxx[lj - 1][li - 1] : T(0);
-    const T e10 = lj > 0 ? sm.sxx[lj - 1][li] : T(0);
-    const T e01 = li > 0 ? sm.sxx[lj][li - 1] : T(0);
-    mue[s] = el2d::vertex_modulus<T>(mu0, e00, e10, e01, e, act, on);
+    mue[s] = el2d::vertex_modulus<T>(mu0, sm.sxx[r - 1][c - 1], sm.sxx[r - 1][c], sm.sxx[r][c - 1], e, act, on);
   }
   __syncthreads();
 
   const T rh = T(1.0 / g.h), h = T(g.h);
   const T ca = T(A.st->a), cc = T(A.st->c), dt = T(A.st->dt);
-  const bool cl0 = g.clamp[0], cl1 = g.clamp[1], cl2 = g.clamp[2], cl3 = g.clamp[3];
+  // reflected-ghost multipliers of clamped sides (0 on other sides), applied on the
+  // first / last row and column of the grid
+  const T gb = g.clamp[2] ? T(-1) : T(0), gt = g.clamp[3] ? T(-1) : T(0);
+  const T gl = g.clamp[0] ? T(-1) : T(0), gr = g.clamp[1] ? T(-1) : T(0);
   double acc = 0.0;
   for (int k = 0; k < K; ++k) {
     // (B) stresses of the cell and the vertex at every position of the window
 #pragma unroll
     for (int s = 0; s < PPT; ++s) {
-      const int lj = lw + s * RSTEP, j = je + lj;
+      const int lj = lw + s * RSTEP, j = je + lj, r = lj + 1;
       const T uxs = ux[s], uys = uy[s];
-      const T ux_r = li + 1 < EX ? sm.dx[lj][li + 1] : T(0);
-      const T uy_u = lj + 1 < EY ? sm.dy[lj + 1][li] : T(0);
-      const T ux_dn = lj > 0 ? sm.dx[lj - 1][li] : T(0);
-      const T uy_lf = li > 0 ? sm.dy[lj][li - 1] : T(0);
+      const T ux_r = sm.dx[r][c + 1];
+      const T uy_u = sm.dy[r + 1][c];
+      const T ux_dn = sm.dx[r - 1][c];
+      const T uy_lf = sm.dy[r][c - 1];
       // reflected ghosts of clamped sides, as the one-sweep kernel stages them
-      const T ux_below = j == 0 ? (cl2 ? -uxs : T(0)) : ux_dn;
-      const T uy_left = i == 0 ? (cl0 ? -uys : T(0)) : uy_lf;
-      const T ux_here = j == ny ? (cl3 ? -ux_dn : T(0)) : uxs;
-      const T uy_here = i == nx ? (cl1 ? -uy_lf : T(0)) : uys;
+      const T ux_below = j == 0 ? gb * uxs : ux_dn;
+      const T uy_left = i == 0 ? gl * uys : uy_lf;
+      const T ux_here = j == ny ? gt * ux_dn : uxs;
+      const T uy_here = i == nx ? gr * uy_lf : uys;
       const T exx = (ux_r - uxs) * rh;
       const T eyy = (uy_u - uys) * rh;
-      el2d::normal_stress<T>(lam[s], mu2[s], exx, eyy, sm.sxx[lj][li], sm.syy[lj][li]);
-      sm.tau[lj][li] = mue[s] * el2d::shear_strain<T>(ux_here, ux_below, uy_here, uy_left, rh);
+      el2d::normal_stress<T>(lam[s], mu2[s], exx, eyy, sm.sxx[r][c], sm.syy[r][c]);
+      sm.tau[r][c] = mue[s] * el2d::shear_strain<T>(ux_here, ux_below, uy_here, uy_left, rh);
     }
     __syncthreads();
     // (C) residuals and the damped update of every free unknown
 #pragma unroll
     for (int s = 0; s < PPT; ++s) {
-      const int lj = lw + s * RSTEP;
-      const T sxx_l = li > 0 ? sm.sxx[lj][li - 1] : T(0);
-      const T syy_d = lj > 0 ? sm.syy[lj - 1][li] : T(0);
-      const T tau_u = lj + 1 < EY ? sm.tau[lj + 1][li] : T(0);
-      const T tau_r = li + 1 < EX ? sm.tau[lj][li + 1] : T(0);
-      const T t0 = sm.tau[lj][li];
-      const bool inner = CHECK && k == K - 1 && li >= K && li < EX - K && lj >= K && lj < EY - K;
-      if (freex & (1u << s)) {
-        const T rx = el2d::residual<T>(bx[s], h, sm.sxx[lj][li], sxx_l, tau_u, t0);
-        el2d::update<T>(ca, cc, dt, rx, ux[s], vx[s]);
-        if (inner) acc += (double)rx * (double)rx;
+      const int lj = lw + s * RSTEP, r = lj + 1;
+      const T t0 = sm.tau[r][c];
+      const T rx = el2d::residual<T>(bx[s], h, sm.sxx[r][c], sm.sxx[r][c - 1], sm.tau[r + 1][c], t0);
+      const T ry = el2d::residual<T>(by[s], h, sm.syy[r][c], sm.syy[r - 1][c], sm.tau[r][c + 1], t0);
+      T ux2 = ux[s], vx2 = vx[s], uy2 = uy[s], vy2 = vy[s];
+      el2d::update<T>(ca, cc, dt, rx, ux2, vx2);
+      el2d::update<T>(ca, cc, dt, ry, uy2, vy2);
+      const bool frx = fx[s] != T(0), fry = fy[s] != T(0);
+      ux[s] = frx ? ux2 : ux[s];
+      vx[s] = frx ? vx2 : vx[s];
+      uy[s] = fry ? uy2 : uy[s];
+      vy[s] = fry ? vy2 : vy[s];
+      if (CHECK && k == K - 1) {
+        const bool inner = li >= K && li < EX - K && lj >= K && lj < EY - K;
+        const double rx2 = (inner && frx) ? (double)rx * (double)rx : 0.0;
+        const double ry2 = (inner && fry) ? (double)ry * (double)ry : 0.0;
+        acc += rx2 + ry2;
       }
-      if (freey & (1u << s)) {
-        const T ry = el2d::residual<T>(by[s], h, sm.syy[lj][li], syy_d, tau_r, t0);
-        el2d::update<T>(ca, cc, dt, ry, uy[s], vy[s]);
-        if (inner) acc += (double)ry * (double)ry;
-      }
-      sm.dx[lj][li] = ux[s];
-      sm.dy[lj][li] = uy[s];
+      sm.dx[r][c] = ux[s];
+      sm.dy[r][c] = uy[s];
     }
     __syncthreads();
   }
@@ -157,18 +174,10 @@ __global__ __launch_bounds__(NT) void el2d_tb_kernel(ElGeom g, ElSweep<T> A, int
     if (li < K || li >= EX - K || lj < K || lj >= EY - K) continue;
     if (i > nx || j > ny) continue;
     const long p = (long)j * px + i;
-    if (j < ny) {
-      A.uout[p] = ux[s];
-      A.v[p] = vx[s];
-    } else {
-      A.uout[p] = T(0);
-    }
-    if (i < nx) {
-      A.uout[pl + p] = uy[s];
-      A.v[pl + p] = vy[s];
-    } else {
-      A.uout[pl + p] = T(0);
-    }
+    A.uout[p] = j < ny ? ux[s] : T(0);
+    if (j < ny) A.v[p] = vx[s];
+    A.uout[pl + p] = i < nx ? uy[s] : T(0);
+    if (i < nx) A.v[pl + p] = vy[s];
   }
   if (CHECK) {
     const double sum = block_sum(acc, sm.red);
