@@ -48,6 +48,8 @@ def parse():
                     help="cantilever2d (design steps, the default line) or, for sweep throughput only: "
                          "heat_batch64, cantilever3d_128x64x64, multimaterial3d_256x128x128")
     ap.add_argument("--sweeps", type=int, default=2000, help="sweep-throughput legs: sweeps to time")
+    ap.add_argument("--adapt", action="store_true",
+                    help="re-choose the damping at every check from the state's Rayleigh quotient")
     ap.add_argument("--ttd-steps", type=int, default=0,
                     help="time to converged design: run this many design steps in FP32 (refined, graphs, "
                          "multi-sweep launches) and in FP64 (one sweep per launch, no graphs)")
@@ -145,7 +147,7 @@ def ttd_leg(args):
         g = ctx.new_cells()
         comp = torch.zeros(2, dtype=torch.float64, device="cuda")
         apt = dict(theta=args.theta, tol=args.tol, check_every=100, refine=(mode == "fp32"),
-                   use_graph=(mode == "fp32"))
+                   use_graph=(mode == "fp32"), adapt=args.adapt)
         sweeps, hist = 0, []
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -164,7 +166,7 @@ def ttd_leg(args):
         res[m].pop("phi_final")
     out = {"metric": "time to converged design FP32 vs FP64", "config": {
         "workload": f"cantilever2d_{args.nx}x{args.ny}", "design_steps": args.ttd_steps, "tol": args.tol,
-        "theta": args.theta},
+        "theta": args.theta, "adaptive_damping": args.adapt},
         "fp32_refined_graph": res["fp32"], "fp64_plain": res["fp64"],
         "speedup": res["fp64"]["seconds"] / res["fp32"]["seconds"],
         "rel_compliance_diff": abs(res["fp32"]["compliance"] - res["fp64"]["compliance"]) /
@@ -198,7 +200,7 @@ def main():
     v = ctx.new_state()
     g = ctx.new_cells()
     comp = torch.zeros(2, dtype=torch.float64, device="cuda")
-    apt = dict(theta=args.theta, tol=args.tol, check_every=100, refine=True)
+    apt = dict(theta=args.theta, tol=args.tol, check_every=100, refine=True, adapt=args.adapt)
     records = []
 
     def step():
@@ -239,7 +241,7 @@ def main():
         "dtype": "f32 sweeps, f64 state/norms",
         "data": "synthetic",
         "config": {"workload": f"cantilever2d_{args.nx}x{args.ny}", "cells": ncell, "theta": args.theta,
-                   "tol": args.tol, "sweeps_timed": total_sweeps,
+                   "adaptive_damping": args.adapt, "tol": args.tol, "sweeps_timed": total_sweeps,
                    "compliance": comp[0].item()},
     }
     if sweeps_timed > 0:

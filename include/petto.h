@@ -103,7 +103,11 @@ typedef struct {
  *  velocity carries over, so in exact arithmetic this is the same iteration.
  *  use_graph: replay captured blocks of check_every sweeps instead of launching
  *  each sweep from the host.  replay_iters > 0: run exactly that many sweeps (a
- *  multiple of check_every), ignoring tol. */
+ *  multiple of check_every), ignoring tol.
+ *  adapt: after every check block re-choose the damping from the state u at the
+ *  block boundary: theta = max(theta_given, 1 / (4 lam)) with the Rayleigh quotient
+ *  lam = u.K u / (h^d u.u), which critically damps the mode of the current state
+ *  (needs dt <= 0: the step follows theta).  The velocity carries over. */
 typedef struct {
   double theta;
   double dt;
@@ -113,6 +117,7 @@ typedef struct {
   int32_t refine;
   int32_t use_graph;
   int32_t replay_iters;
+  int32_t adapt;
 } petto_apt_params;
 
 /* Design update controls (Sections 2.4, 3.1).  phi' = phi - alpha_h g / max|g|
@@ -137,7 +142,8 @@ typedef struct {
   int32_t pad_;
   double rel_res;           /* rho at the last check (refine: double residual) */
   double r_pde;             /* Eq. 3.5: sqrt(sum R^2) / number of cells */
-  double dt;                /* pseudo-time step used */
+  double dt;                /* pseudo-time step at the end */
+  double theta;             /* damping at the end */
 } petto_solve_info;
 
 typedef struct {
@@ -206,13 +212,13 @@ double petto_last_sweep_ms(const petto_ctx *ctx, int64_t *sweeps);
 /* Enable (1) or disable (0) the sweep timing above (off by default). */
 petto_status petto_set_timing(petto_ctx *ctx, int32_t on);
 
-/* Sweeps per launch of the 2D elastic relaxation.  k in {2, 4, 5, 8, 10}: each launch
- * stages an LDS window of the grid and runs k sweeps on it (results bit-identical
- * to one sweep per launch); k = 1: one sweep per launch; k = 0 (default for FP32
- * contexts): time the candidates on the first solve and keep the fastest.  A
- * block of check_every sweeps uses k only when check_every is a multiple of 2k,
- * else one sweep per launch.  FP64 contexts default to 1.  3D and heat contexts
- * always use one sweep per launch. */
+/* Sweeps per launch of the 2D relaxations (elastic and heat).  k in {2, 4, 5, 8, 10}
+ * (FP64: {2, 4, 5}): each launch stages an LDS window of the grid and runs k sweeps
+ * on it (results bit-identical to one sweep per launch); k = 1: one sweep per
+ * launch; k = 0 (default for FP32 contexts): time the candidates on the first
+ * solve and keep the fastest.  A block of check_every sweeps uses k only when
+ * check_every is a multiple of 2k, else one sweep per launch.  FP64 contexts
+ * default to 1; 3D contexts stream along z with one sweep per launch. */
 petto_status petto_set_blocking(petto_ctx *ctx, int32_t k);
 
 /* The sweeps per launch in use (0: not chosen yet). */

@@ -32,6 +32,8 @@ class SolveResult:
     r_pde: float
     converged: bool
     diverged: bool
+    theta: float = 0.0
+    dt: float = 0.0
 
 
 def default_dt(h, ndim, m_max, theta):
@@ -42,10 +44,30 @@ def default_dt(h, ndim, m_max, theta):
     return h * h / (2.0 * ndim * m_max)
 
 
+def adapted_theta(u, r, F, hd, theta_min, theta_max=1e6):
+    """Damping that critically damps the mode of the current state: with the
+    Rayleigh quotient lam = u.Ku / (h^d u.u) (u.Ku = u.F - u.r) of the pseudo-time
+    operator, the damped wave theta u'' + u' + lam u = 0 is critically damped at
+    theta = 1 / (4 lam); never below theta_min.  Returns None when u is zero."""
+    uu = float(np.sum(u * u))
+    if uu <= 0.0:
+        return None
+    uKu = float(np.sum(u * F)) - float(np.sum(u * r))
+    if not uKu > 0.0:
+        return None
+    lam = uKu / (hd * uu)
+    return min(max(theta_min, 0.25 / lam), theta_max)
+
+
 def apt_solve(residual_fn, u0, *, dt, theta, hd, fnorm, ncell, tol=1e-6, check_every=100,
-              max_iter=10**7, n_iter=None, v0=None, div_factor=1e4):
+              max_iter=10**7, n_iter=None, v0=None, div_factor=1e4, adapt=None):
     """Run sweeps from (u0, v0=0).  With n_iter given, run exactly that many sweeps
-    (the stop rule is still evaluated for reporting)."""
+    (the stop rule is still evaluated for reporting).  adapt = (F, dt_of_theta):
+    after every checking sweep that does not stop the iteration, re-choose theta
+    with `adapted_theta` from the state that sweep produced (floor: the given
+    theta) and the step dt_of_theta(theta); the new values apply from the next
+    sweep."""
+    theta_min = theta
     u = np.array(u0, dtype=np.float64)
     v = np.zeros_like(u) if v0 is None else np.array(v0, dtype=np.float64)
     it = 0
@@ -73,6 +95,10 @@ def apt_solve(residual_fn, u0, *, dt, theta, hd, fnorm, ncell, tol=1e-6, check_e
             if n_iter is None and rho <= tol:
                 converged = True
                 break
+            if adapt is not None and it < limit:
+                th = adapted_theta(u, residual_fn(u), adapt[0], hd, theta_min)
+                if th is not None:
+                    theta, dt = th, adapt[1](th)
     if n_iter is not None:
         converged = rho <= tol
-    return SolveResult(u, v, it, rho, r_pde, converged, diverged)
+    return SolveResult(u, v, it, rho, r_pde, converged, diverged, theta, dt)

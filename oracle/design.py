@@ -76,6 +76,7 @@ class AptParams:
     tol: float = 1e-6
     check_every: int = 100
     max_iter: int = 10**7
+    adapt: bool = False           # re-choose theta at every check (critical damping of the state's mode)
 
 
 def stiffness(E, prob):
@@ -105,9 +106,12 @@ def solve(phi, prob, u0=None, params=AptParams(), n_iter=None):
                                                     params.theta)
     fnorm = float(np.sqrt(np.sum(F * F)))
     rfn = assembled_residual(stiffness(E, prob), F, prob)
+    mmax = wave_modulus_max(E, prob)
+    adapt = (F, lambda th: apt.default_dt(prob.h, prob.ndim, mmax, th)) if params.adapt else None
     res = apt.apt_solve(rfn, u0, dt=dt, theta=params.theta,
                         hd=prob.h ** prob.ndim, fnorm=fnorm, ncell=prob.ncell, tol=params.tol,
-                        check_every=params.check_every, max_iter=params.max_iter, n_iter=n_iter)
+                        check_every=params.check_every, max_iter=params.max_iter, n_iter=n_iter,
+                        adapt=adapt)
     return res, dt
 
 

@@ -33,7 +33,7 @@ class AptParams(C.Structure):
     _fields_ = [
         ("theta", C.c_double), ("dt", C.c_double), ("tol", C.c_double), ("max_iter", C.c_int32),
         ("check_every", C.c_int32), ("refine", C.c_int32), ("use_graph", C.c_int32),
-        ("replay_iters", C.c_int32),
+        ("replay_iters", C.c_int32), ("adapt", C.c_int32),
     ]
 
 
@@ -47,11 +47,11 @@ class PhaseParams(C.Structure):
 class SolveInfo(C.Structure):
     _fields_ = [
         ("iters", C.c_int32), ("status", C.c_int32), ("outer", C.c_int32), ("pad_", C.c_int32),
-        ("rel_res", C.c_double), ("r_pde", C.c_double), ("dt", C.c_double),
+        ("rel_res", C.c_double), ("r_pde", C.c_double), ("dt", C.c_double), ("theta", C.c_double),
     ]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k in ("iters", "status", "outer", "rel_res", "r_pde", "dt")}
+        return {k: getattr(self, k) for k in ("iters", "status", "outer", "rel_res", "r_pde", "dt", "theta")}
 
 
 class PhaseInfo(C.Structure):

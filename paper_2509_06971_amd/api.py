@@ -92,12 +92,13 @@ class Context:
 
     @staticmethod
     def apt_params(theta=1.0, dt=0.0, tol=1e-6, max_iter=10**8, check_every=100, refine=False,
-                   use_graph=True, replay_iters=0):
+                   use_graph=True, replay_iters=0, adapt=False):
         p = L.AptParams()
         p.theta, p.dt, p.tol = float(theta), float(dt), float(tol)
         p.max_iter, p.check_every = int(max_iter), int(check_every)
         p.refine, p.use_graph = int(bool(refine)), int(bool(use_graph))
         p.replay_iters = int(replay_iters)
+        p.adapt = int(bool(adapt))
         return p
 
     @staticmethod

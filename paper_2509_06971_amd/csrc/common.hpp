@@ -23,8 +23,18 @@ struct SolveState {
   double sumsq;           // sum r^2 of the last check
   double theta;
   double hd;              // h^d
+  double dt_scale;        // automatic step: dt = dt_scale * sqrt(theta)
+  double theta_min;       // adaptive damping never goes below this
   int32_t iters, done, status, checks;
   int32_t max_iter, check_every, replay, first_seen;
+  int32_t adapt, pad2, pad3, pad4;
+};
+
+// State-layout range and uniform source of one design (Rayleigh-quotient sums).
+struct StateRange {
+  long off;
+  long n;
+  double fsrc;            // used when the dense load is absent
 };
 
 // What the host polls after each block of sweeps (one ring slot per block).

@@ -42,9 +42,12 @@ __global__ void setup_kernel(SetupArgs A) {
     const double h = A.h[d];
     const double mmax = mx * A.m0;
     double dt = A.dt_user;
+    s.dt_scale = h / sqrt(2.0 * A.ndim * mmax);
     if (!(dt > 0.0)) {
-      dt = A.theta > 0.0 ? h * sqrt(A.theta / (2.0 * A.ndim * mmax)) : h * h / (2.0 * A.ndim * mmax);
+      dt = A.theta > 0.0 ? s.dt_scale * sqrt(A.theta) : h * h / (2.0 * A.ndim * mmax);
     }
+    s.theta_min = A.theta;
+    s.adapt = A.adapt;
     double hd = h * h;
     if (A.ndim == 3) hd *= h;
     s.dt = dt;
@@ -109,6 +112,26 @@ __global__ __launch_bounds__(kBlock) void finalize_kernel(FinalizeArgs A) {
       } else if (A.mode == 1) {
         s.iters += s.check_every;   // the sweeps of this block will run
       }
+      if (!s.done && s.adapt && A.prq != nullptr) {
+        // critical damping of the mode of the state at this block boundary
+        double uu = 0.0, uf = 0.0, ur = 0.0;
+        const double* q = A.prq + (long)d * A.rq_blocks * 3;
+        for (int b = 0; b < A.rq_blocks; ++b) {
+          uu += q[3 * b];
+          uf += q[3 * b + 1];
+          ur += q[3 * b + 2];
+        }
+        const double uku = uf - ur;
+        if (uu > 0.0 && uku > 0.0) {
+          const double lam = uku / (s.hd * uu);
+          const double th = fmin(fmax(s.theta_min, 0.25 / lam), 1e6);
+          const double dt = s.dt_scale * sqrt(th);
+          s.theta = th;
+          s.dt = dt;
+          s.a = th / (th + dt);
+          s.c = dt / ((th + dt) * s.hd);
+        }
+      }
     }
   }
   __syncthreads();
@@ -172,6 +195,31 @@ __global__ void fold_kernel(double* u, float* d, long n, const int* all_done) {
   }
 }
 
+template <typename U, typename R>
+__global__ __launch_bounds__(kBlock) void rq_kernel(const U* __restrict__ u, const R* __restrict__ r,
+                                                    const double* __restrict__ F, const StateRange* ranges,
+                                                    double* prq) {
+  __shared__ double red[kBlock / kWave];
+  const int d = blockIdx.y;
+  const StateRange R0 = ranges[d];
+  double uu = 0.0, uf = 0.0, ur = 0.0;
+  for (long q = (long)blockIdx.x * kBlock + threadIdx.x; q < R0.n; q += (long)gridDim.x * kBlock) {
+    const double x = (double)u[R0.off + q];
+    uu += x * x;
+    uf += x * (F != nullptr ? F[R0.off + q] : R0.fsrc);
+    ur += x * (double)r[R0.off + q];
+  }
+  const double a = block_sum(uu, red);
+  const double b = block_sum(uf, red);
+  const double c = block_sum(ur, red);
+  if (threadIdx.x == 0) {
+    double* o = prq + ((long)d * gridDim.x + blockIdx.x) * 3;
+    o[0] = a;
+    o[1] = b;
+    o[2] = c;
+  }
+}
+
 inline int grid_for(long n) {
   long b = (n + kBlock - 1) / kBlock;
   if (b > 4096) b = 4096;
@@ -190,6 +238,18 @@ void launch_material(const T* phi, T* E, double* E64, const CellRange* ranges, i
                      ranges, nphase, phase_stride, e0, emin, p, ep[0], ep[1], ep[2], partial_max,
                      blocks_per_design);
 }
+
+template <typename U, typename R>
+void launch_rq(const U* u, const R* r, const double* F, const StateRange* ranges, int ndes, int bpd,
+               double* prq, hipStream_t s) {
+  hipLaunchKernelGGL((rq_kernel<U, R>), dim3(bpd, ndes), dim3(kBlock), 0, s, u, r, F, ranges, prq);
+}
+template void launch_rq<float, float>(const float*, const float*, const double*, const StateRange*, int, int,
+                                      double*, hipStream_t);
+template void launch_rq<double, double>(const double*, const double*, const double*, const StateRange*, int, int,
+                                        double*, hipStream_t);
+template void launch_rq<double, float>(const double*, const float*, const double*, const StateRange*, int, int,
+                                       double*, hipStream_t);
 
 void launch_setup(const SetupArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(setup_kernel, dim3(a.ndes), dim3(kWave), 0, s, a);

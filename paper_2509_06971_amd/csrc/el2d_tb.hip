@@ -175,9 +175,9 @@ __global__ __launch_bounds__(NT) void el2d_tb_kernel(ElGeom g, ElSweep<T> A, int
     if (i > nx || j > ny) continue;
     const long p = (long)j * px + i;
     A.uout[p] = j < ny ? ux[s] : T(0);
-    if (j < ny) A.v[p] = vx[s];
+    if (j < ny) A.vout[p] = vx[s];
     A.uout[pl + p] = i < nx ? uy[s] : T(0);
-    if (i < nx) A.v[pl + p] = vy[s];
+    if (i < nx) A.vout[pl + p] = vy[s];
   }
   if (CHECK) {
     const double sum = block_sum(acc, sm.red);

@@ -1,12 +1,11 @@
-// 3D staggered-grid elasticity: fused APT sweep, residual, refinement residual and
-// sensitivity kernels for gfx950.
+// 3D staggered-grid elasticity: the sensitivity kernel (per-cell bilinear energy
+// of the normal strains at cells and the engineering shear strains on the xy-,
+// xz- and yz-edges, Eqs. 3.9-3.10 in three dimensions), with compliance partials.
+// The sweep kernels live in el3d_stream.hip.
 //
 // A workgroup owns TX x TY x TZ grid positions; position (i, j, k) carries u_x, u_y,
 // u_z on the faces normal to x, y, z.  The halo tile of u (ghosts of clamped sides
-// reflected) and of the cell modulus sits in LDS; normal stresses are formed at
-// cells, the three shear stresses on the xy-, xz- and yz-edges, then the
-// divergence plus load gives the residual r of every unknown (Eqs. 3.6, 3.9 and
-// 3.10 in three dimensions) and the damped update of Eq. 3.12 is applied.
+// reflected) sits in LDS.
 #include "kernels.hpp"
 #include "material.hpp"
 
@@ -34,38 +33,9 @@ struct Dims {
 };
 
 template <typename T>
-struct Smem3 {
-  T ux[Dims<T>::NH], uy[Dims<T>::NH], uz[Dims<T>::NH], E[Dims<T>::NH];
-  T sxx[Dims<T>::NC], syy[Dims<T>::NC], szz[Dims<T>::NC];
-  T txy[Dims<T>::NXY], txz[Dims<T>::NXZ], tyz[Dims<T>::NYZ];
-  double red[kBlock / kWave];
-};
-
-template <typename T>
 __device__ inline int H(int li, int lj, int lk) {
   return (lk * Dims<T>::LY + lj) * Dims<T>::LX + li;
 }
-template <typename T>
-__device__ inline int C(int li, int lj, int lk) {
-  return (lk * (Dims<T>::TY + 1) + lj) * (Dims<T>::TX + 1) + li;
-}
-template <typename T>
-__device__ inline int IXY(int li, int lj, int lk) {   // li,lj >= 1, lk >= 1
-  return ((lk - 1) * (Dims<T>::TY + 1) + (lj - 1)) * (Dims<T>::TX + 1) + (li - 1);
-}
-template <typename T>
-__device__ inline int IXZ(int li, int lj, int lk) {
-  return ((lk - 1) * Dims<T>::TY + (lj - 1)) * (Dims<T>::TX + 1) + (li - 1);
-}
-template <typename T>
-__device__ inline int IYZ(int li, int lj, int lk) {
-  return ((lk - 1) * (Dims<T>::TY + 1) + (lj - 1)) * Dims<T>::TX + (li - 1);
-}
-
-__device__ inline bool pinned3(const uint32_t* pins, long k) {
-  return pins != nullptr && ((pins[k >> 5] >> (k & 31)) & 1u);
-}
-
 // Value of component `a` at face position (i, j, k) including reflected ghosts.
 template <typename T>
 __device__ inline T face_value(const ElGeom& g, const T* __restrict__ u, int a, int i, int j, int k) {
@@ -115,189 +85,6 @@ __device__ inline bool axis_ok(int idx, int n, int clo, int chi, bool& on) {
   if (idx == 0) { on = true; return clo != 0; }
   if (idx == n) { on = true; return chi != 0; }
   return true;
-}
-
-template <typename T, int MODE>
-__global__ __launch_bounds__(kBlock) void el3d_kernel(ElGeom g, ElSweep<T> A, int tiles_x, int tiles_y,
-                                                      int ntiles) {
-  using D = Dims<T>;
-  if (MODE == kSweep || MODE == kCheck || (MODE == kRefine && A.st != nullptr)) {
-    if (A.st->done) return;
-  }
-  __shared__ Smem3<T> sm;
-  const int tile = xcd_tile(blockIdx.x, ntiles);
-  const int tz = tile / (tiles_x * tiles_y);
-  const int trem = tile - tz * tiles_x * tiles_y;
-  const int tyi = trem / tiles_x, txi = trem - tyi * tiles_x;
-  const int i0 = txi * D::TX, j0 = tyi * D::TY, k0 = tz * D::TZ;
-  const int nx = g.nx, ny = g.ny, nz = g.nz;
-  const long pl = g.plane;
-
-  // positions of this thread: x from lane, (y, z) from the wave and the repeat index
-  T vv[D::RPT][3], bb[D::RPT][3];
-#pragma unroll
-  for (int r = 0; r < D::RPT; ++r) {
-    const int q = threadIdx.x + r * kBlock;
-    const int pi = q % D::TX, pj = (q / D::TX) % D::TY, pk = q / (D::TX * D::TY);
-    const int i = i0 + pi, j = j0 + pj, k = k0 + pk;
-    const long p = ((long)k * g.py + j) * g.px + i;
-    const bool in = i <= nx && j <= ny && k <= nz;
-    const bool ok[3] = {in && j < ny && k < nz, in && i < nx && k < nz, in && i < nx && j < ny};
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      vv[r][a] = T(0);
-      if ((MODE == kSweep || MODE == kCheck) && ok[a]) vv[r][a] = A.v[a * pl + p];
-      bb[r][a] = ok[a] ? A.b[a * pl + p] : T(0);
-    }
-  }
-
-  load_tile3<T>(g, A.uin, A.E, i0, j0, k0, sm.ux, sm.uy, sm.uz, sm.E);
-  __syncthreads();
-
-  const T rh = T(1.0 / g.h);
-  const T h2 = T(g.h * g.h);
-  const T lam0 = T(g.lam0), mu0 = T(g.mu0), q0 = T(0.25) * T(g.mu0);
-  // normal stresses at cells local [0,TX]x[0,TY]x[0,TZ]
-  for (int idx = threadIdx.x; idx < D::NC; idx += kBlock) {
-    const int lk = idx / ((D::TX + 1) * (D::TY + 1));
-    const int rem = idx - lk * (D::TX + 1) * (D::TY + 1);
-    const int lj = rem / (D::TX + 1), li = rem - lj * (D::TX + 1);
-    const int hc = H<T>(li, lj, lk);
-    const T e = sm.E[hc];
-    const T exx = (sm.ux[H<T>(li + 1, lj, lk)] - sm.ux[hc]) * rh;
-    const T eyy = (sm.uy[H<T>(li, lj + 1, lk)] - sm.uy[hc]) * rh;
-    const T ezz = (sm.uz[H<T>(li, lj, lk + 1)] - sm.uz[hc]) * rh;
-    const T lam = e * lam0, mu2 = T(2) * e * mu0;
-    const T lt = lam * (exx + eyy + ezz);
-    sm.sxx[idx] = lt + mu2 * exx;
-    sm.syy[idx] = lt + mu2 * eyy;
-    sm.szz[idx] = lt + mu2 * ezz;
-  }
-  // xy edges: (vi, vj, ck); cells around: (vi-1..vi, vj-1..vj, ck)
-  for (int idx = threadIdx.x; idx < D::NXY; idx += kBlock) {
-    const int lk = 1 + idx / ((D::TX + 1) * (D::TY + 1));
-    const int rem = idx % ((D::TX + 1) * (D::TY + 1));
-    const int lj = 1 + rem / (D::TX + 1), li = 1 + rem % (D::TX + 1);
-    const int vi = i0 - 1 + li, vj = j0 - 1 + lj, ck = k0 - 1 + lk;
-    bool on = false;
-    bool act = vi <= nx && vj <= ny && ck < nz;
-    act = act && axis_ok(vi, nx, g.clamp[0], g.clamp[1], on);
-    act = act && axis_ok(vj, ny, g.clamp[2], g.clamp[3], on);
-    T t = T(0);
-    if (act) {
-      const T gam = (sm.ux[H<T>(li, lj, lk)] - sm.ux[H<T>(li, lj - 1, lk)]) * rh +
-                    (sm.uy[H<T>(li, lj, lk)] - sm.uy[H<T>(li - 1, lj, lk)]) * rh;
-      const T m = q0 * (sm.E[H<T>(li - 1, lj - 1, lk)] + sm.E[H<T>(li, lj - 1, lk)] +
-                        sm.E[H<T>(li - 1, lj, lk)] + sm.E[H<T>(li, lj, lk)]);
-      t = on ? T(2) * m * gam : m * gam;
-    }
-    sm.txy[idx] = t;
-  }
-  // xz edges: (vi, cj, vk); cells (vi-1..vi, cj, vk-1..vk)
-  for (int idx = threadIdx.x; idx < D::NXZ; idx += kBlock) {
-    const int lk = 1 + idx / ((D::TX + 1) * D::TY);
-    const int rem = idx % ((D::TX + 1) * D::TY);
-    const int lj = 1 + rem / (D::TX + 1), li = 1 + rem % (D::TX + 1);
-    const int vi = i0 - 1 + li, cj = j0 - 1 + lj, vk = k0 - 1 + lk;
-    bool on = false;
-    bool act = vi <= nx && cj < ny && vk <= nz;
-    act = act && axis_ok(vi, nx, g.clamp[0], g.clamp[1], on);
-    act = act && axis_ok(vk, nz, g.clamp[4], g.clamp[5], on);
-    T t = T(0);
-    if (act) {
-      const T gam = (sm.ux[H<T>(li, lj, lk)] - sm.ux[H<T>(li, lj, lk - 1)]) * rh +
-                    (sm.uz[H<T>(li, lj, lk)] - sm.uz[H<T>(li - 1, lj, lk)]) * rh;
-      const T m = q0 * (sm.E[H<T>(li - 1, lj, lk - 1)] + sm.E[H<T>(li, lj, lk - 1)] +
-                        sm.E[H<T>(li - 1, lj, lk)] + sm.E[H<T>(li, lj, lk)]);
-      t = on ? T(2) * m * gam : m * gam;
-    }
-    sm.txz[idx] = t;
-  }
-  // yz edges: (ci, vj, vk); cells (ci, vj-1..vj, vk-1..vk)
-  for (int idx = threadIdx.x; idx < D::NYZ; idx += kBlock) {
-    const int lk = 1 + idx / (D::TX * (D::TY + 1));
-    const int rem = idx % (D::TX * (D::TY + 1));
-    const int lj = 1 + rem / D::TX, li = 1 + rem % D::TX;
-    const int ci = i0 - 1 + li, vj = j0 - 1 + lj, vk = k0 - 1 + lk;
-    bool on = false;
-    bool act = ci < nx && vj <= ny && vk <= nz;
-    act = act && axis_ok(vj, ny, g.clamp[2], g.clamp[3], on);
-    act = act && axis_ok(vk, nz, g.clamp[4], g.clamp[5], on);
-    T t = T(0);
-    if (act) {
-      const T gam = (sm.uy[H<T>(li, lj, lk)] - sm.uy[H<T>(li, lj, lk - 1)]) * rh +
-                    (sm.uz[H<T>(li, lj, lk)] - sm.uz[H<T>(li, lj - 1, lk)]) * rh;
-      const T m = q0 * (sm.E[H<T>(li, lj - 1, lk - 1)] + sm.E[H<T>(li, lj, lk - 1)] +
-                        sm.E[H<T>(li, lj - 1, lk)] + sm.E[H<T>(li, lj, lk)]);
-      t = on ? T(2) * m * gam : m * gam;
-    }
-    sm.tyz[idx] = t;
-  }
-  __syncthreads();
-
-  T ca = T(0), cc = T(0), dt = T(0);
-  if (MODE == kSweep || MODE == kCheck) {
-    ca = T(A.st->a);
-    cc = T(A.st->c);
-    dt = T(A.st->dt);
-  }
-  double acc = 0.0;
-#pragma unroll
-  for (int r = 0; r < D::RPT; ++r) {
-    const int q = threadIdx.x + r * kBlock;
-    const int pi = q % D::TX, pj = (q / D::TX) % D::TY, pk = q / (D::TX * D::TY);
-    const int i = i0 + pi, j = j0 + pj, k = k0 + pk;
-    if (i > nx || j > ny || k > nz) continue;
-    const int li = pi + 1, lj = pj + 1, lk = pk + 1;
-    const long p = ((long)k * g.py + j) * g.px + i;
-    const int hc = H<T>(li, lj, lk);
-    const int cc0 = C<T>(li, lj, lk);
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const long gi = a * pl + p;
-      const bool valid = (a == 0) ? (j < ny && k < nz) : (a == 1) ? (i < nx && k < nz) : (i < nx && j < ny);
-      if (!valid) {
-        if (MODE == kSweep || MODE == kCheck) A.uout[gi] = T(0);
-        else if (MODE == kResid) A.v[gi] = T(0);
-        else A.b32[gi] = 0.f;
-        continue;
-      }
-      const int own = (a == 0) ? i : (a == 1) ? j : k;
-      const int nown = (a == 0) ? nx : (a == 1) ? ny : nz;
-      const bool fix = (own == 0 && g.fixn[2 * a]) || (own == nown && g.fixn[2 * a + 1]) || pinned3(g.pins, gi);
-      T rr = T(0);
-      if (!fix) {
-        if (a == 0) {
-          rr = bb[r][0] + h2 * ((sm.sxx[cc0] - sm.sxx[C<T>(li - 1, lj, lk)]) +
-                                (sm.txy[IXY<T>(li, lj + 1, lk)] - sm.txy[IXY<T>(li, lj, lk)]) +
-                                (sm.txz[IXZ<T>(li, lj, lk + 1)] - sm.txz[IXZ<T>(li, lj, lk)]));
-        } else if (a == 1) {
-          rr = bb[r][1] + h2 * ((sm.syy[cc0] - sm.syy[C<T>(li, lj - 1, lk)]) +
-                                (sm.txy[IXY<T>(li + 1, lj, lk)] - sm.txy[IXY<T>(li, lj, lk)]) +
-                                (sm.tyz[IYZ<T>(li, lj, lk + 1)] - sm.tyz[IYZ<T>(li, lj, lk)]));
-        } else {
-          rr = bb[r][2] + h2 * ((sm.szz[cc0] - sm.szz[C<T>(li, lj, lk - 1)]) +
-                                (sm.txz[IXZ<T>(li + 1, lj, lk)] - sm.txz[IXZ<T>(li, lj, lk)]) +
-                                (sm.tyz[IYZ<T>(li, lj + 1, lk)] - sm.tyz[IYZ<T>(li, lj, lk)]));
-        }
-      }
-      const T uo = (a == 0) ? sm.ux[hc] : (a == 1) ? sm.uy[hc] : sm.uz[hc];
-      if (MODE == kSweep || MODE == kCheck) {
-        const T vn = fix ? vv[r][a] : ca * vv[r][a] + cc * rr;
-        A.v[gi] = vn;
-        A.uout[gi] = fix ? uo : uo + dt * vn;
-      } else if (MODE == kResid) {
-        A.v[gi] = rr;
-      } else {
-        A.b32[gi] = (float)rr;
-      }
-      if (MODE == kCheck || MODE == kRefine) acc += (double)rr * (double)rr;
-    }
-  }
-  if (MODE == kCheck || MODE == kRefine) {
-    const double s = block_sum(acc, sm.red);
-    if (threadIdx.x == 0) A.partial[tile] = s;
-  }
 }
 
 // ------------------------------------------------------------------------------ sensitivity
@@ -422,31 +209,6 @@ void tiles3(const ElGeom& g, int& tx, int& ty, int& tz) {
 
 }  // namespace
 
-int el3d_tiles_prec(const ElGeom& g, bool fp64) {
-  int a, b, c;
-  if (fp64) tiles3<double>(g, a, b, c);
-  else tiles3<float>(g, a, b, c);
-  return a * b * c;
-}
-
-// Tile counts differ per precision; partial buffers are sized for the larger.
-int el3d_tiles(const ElGeom& g) {
-  int a, b, c, d, e, f;
-  tiles3<float>(g, a, b, c);
-  tiles3<double>(g, d, e, f);
-  const int n1 = a * b * c, n2 = d * e * f;
-  return n1 > n2 ? n1 : n2;
-}
-
-template <typename T, int MODE>
-int launch_el3d(const ElGeom& g, const ElSweep<T>& a, hipStream_t s) {
-  int tx, ty, tz;
-  tiles3<T>(g, tx, ty, tz);
-  const int nt = tx * ty * tz;
-  hipLaunchKernelGGL((el3d_kernel<T, MODE>), dim3(nt), dim3(kBlock), 0, s, g, a, tx, ty, nt);
-  return nt;
-}
-
 template <typename U, typename T>
 int launch_el3d_adjoint(const ElGeom& g, const ElAdjoint<U, T>& a, hipStream_t s) {
   int tx, ty, tz;
@@ -456,13 +218,6 @@ int launch_el3d_adjoint(const ElGeom& g, const ElAdjoint<U, T>& a, hipStream_t s
   return nt;
 }
 
-template int launch_el3d<float, kSweep>(const ElGeom&, const ElSweep<float>&, hipStream_t);
-template int launch_el3d<float, kCheck>(const ElGeom&, const ElSweep<float>&, hipStream_t);
-template int launch_el3d<float, kResid>(const ElGeom&, const ElSweep<float>&, hipStream_t);
-template int launch_el3d<double, kSweep>(const ElGeom&, const ElSweep<double>&, hipStream_t);
-template int launch_el3d<double, kCheck>(const ElGeom&, const ElSweep<double>&, hipStream_t);
-template int launch_el3d<double, kResid>(const ElGeom&, const ElSweep<double>&, hipStream_t);
-template int launch_el3d<double, kRefine>(const ElGeom&, const ElSweep<double>&, hipStream_t);
 template int launch_el3d_adjoint<float, float>(const ElGeom&, const ElAdjoint<float, float>&, hipStream_t);
 template int launch_el3d_adjoint<double, float>(const ElGeom&, const ElAdjoint<double, float>&, hipStream_t);
 template int launch_el3d_adjoint<double, double>(const ElGeom&, const ElAdjoint<double, double>&, hipStream_t);

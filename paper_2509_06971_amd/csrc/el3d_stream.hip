@@ -1,0 +1,299 @@
+// 3D staggered-grid elastic sweep, streamed along z (gfx950).
+//
+// A workgroup owns a TX x TY column of grid positions and marches through KZ
+// z-layers.  LDS holds the state and moduli of two consecutive layers (k, k+1)
+// with a one-position xy halo (reflected ghosts of clamped sides filled in), the
+// normal stresses and xy-shear of layer k, and the xz/yz-shear planes at z = k
+// and z = k+1.  Per layer: load layer k+1, form the stresses that need it, then
+// the residuals and the damped update of layer k (Eqs. 3.6, 3.9, 3.10, 3.12).
+// Each state value is read from memory about once per sweep (plus the xy halo).
+#include "el3d_ops.hpp"
+#include "kernels.hpp"
+
+#pragma clang fp contract(off)
+
+namespace petto {
+namespace {
+
+constexpr int TX = 64;
+constexpr int LX = TX + 2;
+
+template <typename T, int TY>
+struct Sm3 {
+  static constexpr int LY = TY + 2;
+  T u[2][3][LY][LX];        // state planes (parity of the layer), with halo
+  T e[2][LY][LX];           // cell moduli of the same layers
+  T sxx[LY][LX], syy[LY][LX];
+  T txy[LY][LX];
+  T txz[2][LY][LX];         // xz shear at z = layer (parity)
+  T tyz[2][LY][LX];
+  double red[TX * TY / kWave];
+};
+
+__device__ __forceinline__ bool pinned3s(const uint32_t* pins, long k) {
+  return pins != nullptr && ((pins[k >> 5] >> (k & 31)) & 1u);
+}
+
+// Component a at face position (i, j, k) with the reflected ghosts of clamped sides
+// (one foreign axis out of range by one); zero elsewhere outside the grid.
+template <typename T>
+__device__ __forceinline__ T face3(const ElGeom& g, const T* __restrict__ u, int a, int i, int j, int k) {
+  int id[3] = {i, j, k};
+  const int n[3] = {g.nx, g.ny, g.nz};
+  if (id[a] < 0 || id[a] > n[a]) return T(0);
+  T sgn = T(1);
+  int out = 0;
+#pragma unroll
+  for (int b = 0; b < 3; ++b) {
+    if (b == a) continue;
+    if (id[b] == -1) { out += 1; sgn = g.clamp[2 * b] ? -sgn : T(0); id[b] = 0; }
+    else if (id[b] == n[b]) { out += 1; sgn = g.clamp[2 * b + 1] ? -sgn : T(0); id[b] = n[b] - 1; }
+    else if (id[b] < -1 || id[b] > n[b]) { out += 2; }
+  }
+  if (out > 1 || sgn == T(0)) return T(0);
+  return sgn * u[(long)a * g.plane + ((long)id[2] * g.py + id[1]) * g.px + id[0]];
+}
+
+template <typename T, int TY>
+__device__ __forceinline__ void load_plane(const ElGeom& g, const T* __restrict__ u, const T* __restrict__ E,
+                                           int i0, int j0, int k, int buf, Sm3<T, TY>& sm) {
+  constexpr int LY = TY + 2;
+  for (int q = threadIdx.x; q < LY * LX; q += TX * TY) {
+    const int b = q / LX, a = q - b * LX;
+    const int i = i0 - 1 + a, j = j0 - 1 + b;
+    sm.u[buf][0][b][a] = face3<T>(g, u, 0, i, j, k);
+    sm.u[buf][1][b][a] = face3<T>(g, u, 1, i, j, k);
+    sm.u[buf][2][b][a] = face3<T>(g, u, 2, i, j, k);
+    T ev = T(0);
+    if (E != nullptr && i >= 0 && i < g.nx && j >= 0 && j < g.ny && k >= 0 && k < g.nz)
+      ev = E[((long)k * g.ny + j) * g.nx + i];
+    sm.e[buf][b][a] = ev;
+  }
+}
+
+// side activity along one axis for an edge index; sets `on` on a side
+__device__ __forceinline__ bool edge_ok(int idx, int n, int clo, int chi, bool& on) {
+  if (idx == 0) { on = true; return clo != 0; }
+  if (idx == n) { on = true; return chi != 0; }
+  return idx > 0 && idx < n;
+}
+
+// xz / yz shear planes at z = kz from state planes (lower = kz-1, upper = kz).
+template <typename T, int TY>
+__device__ __forceinline__ void xz_yz_planes(const ElGeom& g, int i0, int j0, int kz, int lo, int up, int dst,
+                                             T rh, T mu0, Sm3<T, TY>& sm) {
+  constexpr int LY = TY + 2;
+  for (int q = threadIdx.x; q < LY * LX; q += TX * TY) {
+    const int b = q / LX, a = q - b * LX;
+    const int i = i0 - 1 + a, j = j0 - 1 + b;
+    T txz = T(0), tyz = T(0);
+    if (a >= 1 && b >= 1) {
+      // xz edge (i, j+1/2, kz): cells (i-1..i, j, kz-1..kz)
+      bool on = false;
+      bool act = j >= 0 && j < g.ny;
+      act = act && edge_ok(i, g.nx, g.clamp[0], g.clamp[1], on);
+      act = act && edge_ok(kz, g.nz, g.clamp[4], g.clamp[5], on);
+      const T m = el3d::edge_modulus<T>(mu0, sm.e[lo][b][a - 1], sm.e[lo][b][a], sm.e[up][b][a - 1], sm.e[up][b][a],
+                                        act, on);
+      const T gam = el3d::shear_strain<T>(sm.u[up][0][b][a], sm.u[lo][0][b][a], sm.u[up][2][b][a],
+                                          sm.u[up][2][b][a - 1], rh);
+      txz = m * gam;
+      // yz edge (i+1/2, j, kz): cells (i, j-1..j, kz-1..kz)
+      bool on2 = false;
+      bool act2 = i >= 0 && i < g.nx;
+      act2 = act2 && edge_ok(j, g.ny, g.clamp[2], g.clamp[3], on2);
+      act2 = act2 && edge_ok(kz, g.nz, g.clamp[4], g.clamp[5], on2);
+      const T m2 = el3d::edge_modulus<T>(mu0, sm.e[lo][b - 1][a], sm.e[lo][b][a], sm.e[up][b - 1][a], sm.e[up][b][a],
+                                         act2, on2);
+      const T gam2 = el3d::shear_strain<T>(sm.u[up][1][b][a], sm.u[lo][1][b][a], sm.u[up][2][b][a],
+                                           sm.u[up][2][b - 1][a], rh);
+      tyz = m2 * gam2;
+    }
+    sm.txz[dst][b][a] = txz;
+    sm.tyz[dst][b][a] = tyz;
+  }
+}
+
+// sigma_zz of the own cell (i, j, k) from planes cur (k) and up (k+1)
+template <typename T, int TY>
+__device__ __forceinline__ T own_szz(const Sm3<T, TY>& sm, int a, int b, int cur, int up, T rh, T lam0, T mu0) {
+  const T e = sm.e[cur][b][a];
+  const T exx = (sm.u[cur][0][b][a + 1] - sm.u[cur][0][b][a]) * rh;
+  const T eyy = (sm.u[cur][1][b + 1][a] - sm.u[cur][1][b][a]) * rh;
+  const T ezz = (sm.u[up][2][b][a] - sm.u[cur][2][b][a]) * rh;
+  T sxx, syy, szz;
+  el3d::normal_stress<T>(e * lam0, T(2) * (e * mu0), exx, eyy, ezz, sxx, syy, szz);
+  return szz;
+}
+
+template <typename T, int TY, int KZ, int MODE>
+__global__ __launch_bounds__(TX * TY) void el3d_stream_kernel(ElGeom g, ElSweep<T> A, int tiles_x, int tiles_y,
+                                                              int ntiles) {
+  if (MODE == kSweep || MODE == kCheck || (MODE == kRefine && A.st != nullptr)) {
+    if (A.st->done) return;
+  }
+  constexpr int LY = TY + 2;
+  __shared__ Sm3<T, TY> sm;
+  const int tile = xcd_tile(blockIdx.x, ntiles);
+  const int tz = tile / (tiles_x * tiles_y);
+  const int trem = tile - tz * tiles_x * tiles_y;
+  const int tyi = trem / tiles_x, txi = trem - tyi * tiles_x;
+  const int i0 = txi * TX, j0 = tyi * TY, k0 = tz * KZ;
+  const int a = 1 + (int)(threadIdx.x % TX), b = 1 + (int)(threadIdx.x / TX);
+  const int i = i0 - 1 + a, j = j0 - 1 + b;
+  const int nx = g.nx, ny = g.ny, nz = g.nz;
+  const long pl = g.plane;
+  const T rh = T(1.0 / g.h), h2 = T(g.h * g.h);
+  const T lam0 = T(g.lam0), mu0 = T(g.mu0);
+  T ca = T(0), cc = T(0), dt = T(0);
+  if (MODE == kSweep || MODE == kCheck) {
+    ca = T(A.st->a);
+    cc = T(A.st->c);
+    dt = T(A.st->dt);
+  }
+  // prologue: planes k0-1 (into buffer 1) and k0 (buffer 0); xz/yz shear at z = k0
+  // into buffer 0; sigma_zz of the own cell at k0-1
+  load_plane<T, TY>(g, A.uin, A.E, i0, j0, k0 - 1, 1, sm);
+  load_plane<T, TY>(g, A.uin, A.E, i0, j0, k0, 0, sm);
+  __syncthreads();
+  xz_yz_planes<T, TY>(g, i0, j0, k0, 1, 0, 0, rh, mu0, sm);
+  T szz_prev = own_szz<T, TY>(sm, a, b, 1, 0, rh, lam0, mu0);
+  __syncthreads();
+  double acc = 0.0;
+  int cur = 0;
+  const int kend = (k0 + KZ < nz + 1) ? k0 + KZ : nz + 1;
+  for (int k = k0; k < kend; ++k) {
+    const int up = cur ^ 1;
+    // own velocity / right-hand side of layer k
+    const long p = ((long)k * g.py + j) * g.px + i;
+    const bool in = i <= nx && j <= ny;
+    const bool ok[3] = {in && j < ny && k < nz, in && i < nx && k < nz, in && i < nx && j < ny};
+    T vv[3], bb[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      vv[c] = T(0);
+      if ((MODE == kSweep || MODE == kCheck) && ok[c]) vv[c] = A.v[c * pl + p];
+      bb[c] = ok[c] ? A.b[c * pl + p] : T(0);
+    }
+    load_plane<T, TY>(g, A.uin, A.E, i0, j0, k + 1, up, sm);
+    __syncthreads();
+    // normal stresses (cells of layer k) and xy shear (layer k)
+    for (int q = threadIdx.x; q < LY * LX; q += TX * TY) {
+      const int bb2 = q / LX, aa = q - bb2 * LX;
+      T sxx = T(0), syy = T(0), txy = T(0);
+      if (aa + 1 < LX && bb2 + 1 < LY) {
+        const T e = sm.e[cur][bb2][aa];
+        const T exx = (sm.u[cur][0][bb2][aa + 1] - sm.u[cur][0][bb2][aa]) * rh;
+        const T eyy = (sm.u[cur][1][bb2 + 1][aa] - sm.u[cur][1][bb2][aa]) * rh;
+        const T ezz = (sm.u[up][2][bb2][aa] - sm.u[cur][2][bb2][aa]) * rh;
+        T szz;
+        el3d::normal_stress<T>(e * lam0, T(2) * (e * mu0), exx, eyy, ezz, sxx, syy, szz);
+      }
+      if (aa >= 1 && bb2 >= 1) {
+        const int vi = i0 - 1 + aa, vj = j0 - 1 + bb2;
+        bool on = false;
+        bool act = k < nz;
+        act = act && edge_ok(vi, nx, g.clamp[0], g.clamp[1], on);
+        act = act && edge_ok(vj, ny, g.clamp[2], g.clamp[3], on);
+        const T m = el3d::edge_modulus<T>(mu0, sm.e[cur][bb2 - 1][aa - 1], sm.e[cur][bb2 - 1][aa],
+                                          sm.e[cur][bb2][aa - 1], sm.e[cur][bb2][aa], act, on);
+        const T gam = el3d::shear_strain<T>(sm.u[cur][0][bb2][aa], sm.u[cur][0][bb2 - 1][aa], sm.u[cur][1][bb2][aa],
+                                            sm.u[cur][1][bb2][aa - 1], rh);
+        txy = m * gam;
+      }
+      sm.sxx[bb2][aa] = sxx;
+      sm.syy[bb2][aa] = syy;
+      sm.txy[bb2][aa] = txy;
+    }
+    xz_yz_planes<T, TY>(g, i0, j0, k + 1, cur, up, up, rh, mu0, sm);
+    const T szz_cur = own_szz<T, TY>(sm, a, b, cur, up, rh, lam0, mu0);
+    __syncthreads();
+    // residuals and update of the own position at layer k
+    if (in) {
+      T rr[3];
+      rr[0] = el3d::residual<T>(bb[0], h2, sm.sxx[b][a], sm.sxx[b][a - 1], sm.txy[b + 1][a], sm.txy[b][a],
+                                sm.txz[up][b][a], sm.txz[cur][b][a]);
+      rr[1] = el3d::residual<T>(bb[1], h2, sm.syy[b][a], sm.syy[b - 1][a], sm.txy[b][a + 1], sm.txy[b][a],
+                                sm.tyz[up][b][a], sm.tyz[cur][b][a]);
+      rr[2] = el3d::residual<T>(bb[2], h2, szz_cur, szz_prev, sm.txz[cur][b][a + 1], sm.txz[cur][b][a],
+                                sm.tyz[cur][b + 1][a], sm.tyz[cur][b][a]);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const long gi = c * pl + p;
+        if (!ok[c]) {
+          if (MODE == kSweep || MODE == kCheck) A.uout[gi] = T(0);
+          else if (MODE == kResid) A.v[gi] = T(0);
+          else A.b32[gi] = 0.f;
+          continue;
+        }
+        const int own = c == 0 ? i : c == 1 ? j : k;
+        const int nown = c == 0 ? nx : c == 1 ? ny : nz;
+        const bool fix = (own == 0 && g.fixn[2 * c]) || (own == nown && g.fixn[2 * c + 1]) || pinned3s(g.pins, gi);
+        const T r = fix ? T(0) : rr[c];
+        T uo = sm.u[cur][c][b][a], vn = vv[c];
+        if (MODE == kSweep || MODE == kCheck) {
+          if (!fix) el3d::update<T>(ca, cc, dt, r, uo, vn);
+          A.v[gi] = vn;
+          A.uout[gi] = uo;
+        } else if (MODE == kResid) {
+          A.v[gi] = r;
+        } else {
+          A.b32[gi] = (float)r;
+        }
+        if (MODE == kCheck || MODE == kRefine) acc += (double)r * (double)r;
+      }
+    }
+    szz_prev = szz_cur;
+    cur = up;
+    __syncthreads();
+  }
+  if (MODE == kCheck || MODE == kRefine) {
+    const double s = block_sum(acc, sm.red);
+    if (threadIdx.x == 0) A.partial[tile] = s;
+  }
+}
+
+template <typename T> struct Cfg3;
+template <> struct Cfg3<float> { static constexpr int TY = 8, KZ = 8; };
+template <> struct Cfg3<double> { static constexpr int TY = 4, KZ = 8; };
+
+template <typename T>
+void tiles_s(const ElGeom& g, int& tx, int& ty, int& tz) {
+  tx = (g.nx + 1 + TX - 1) / TX;
+  ty = (g.ny + 1 + Cfg3<T>::TY - 1) / Cfg3<T>::TY;
+  tz = (g.nz + 1 + Cfg3<T>::KZ - 1) / Cfg3<T>::KZ;
+}
+
+}  // namespace
+
+int el3d_tiles_prec(const ElGeom& g, bool fp64) {
+  int a, b, c;
+  if (fp64) tiles_s<double>(g, a, b, c);
+  else tiles_s<float>(g, a, b, c);
+  return a * b * c;
+}
+
+int el3d_tiles(const ElGeom& g) {
+  const int n1 = el3d_tiles_prec(g, false), n2 = el3d_tiles_prec(g, true);
+  return n1 > n2 ? n1 : n2;
+}
+
+template <typename T, int MODE>
+int launch_el3d(const ElGeom& g, const ElSweep<T>& a, hipStream_t s) {
+  int tx, ty, tz;
+  tiles_s<T>(g, tx, ty, tz);
+  const int nt = tx * ty * tz;
+  constexpr int TY = Cfg3<T>::TY, KZ = Cfg3<T>::KZ;
+  hipLaunchKernelGGL((el3d_stream_kernel<T, TY, KZ, MODE>), dim3(nt), dim3(TX * TY), 0, s, g, a, tx, ty, nt);
+  return nt;
+}
+
+template int launch_el3d<float, kSweep>(const ElGeom&, const ElSweep<float>&, hipStream_t);
+template int launch_el3d<float, kCheck>(const ElGeom&, const ElSweep<float>&, hipStream_t);
+template int launch_el3d<float, kResid>(const ElGeom&, const ElSweep<float>&, hipStream_t);
+template int launch_el3d<double, kSweep>(const ElGeom&, const ElSweep<double>&, hipStream_t);
+template int launch_el3d<double, kCheck>(const ElGeom&, const ElSweep<double>&, hipStream_t);
+template int launch_el3d<double, kResid>(const ElGeom&, const ElSweep<double>&, hipStream_t);
+template int launch_el3d<double, kRefine>(const ElGeom&, const ElSweep<double>&, hipStream_t);
+
+}  // namespace petto

@@ -6,8 +6,11 @@
 // memory, so converged designs retire without host involvement.  Faces between
 // cells carry the arithmetic-mean conductivity; Dirichlet faces (T = 0 sinks) act
 // through the reflected ghost; other boundary faces are no-flux.
+#include "heat_ops.hpp"
 #include "kernels.hpp"
 #include "material.hpp"
+
+#pragma clang fp contract(off)
 
 namespace petto {
 namespace {
@@ -41,14 +44,8 @@ __device__ inline void load_heat_tile(const HeatDesign& D, const T* __restrict__
   }
 }
 
-__device__ inline int dirichlet_count(const HeatDesign& D, const uint8_t* dir, int i, int j) {
-  const uint8_t* t = dir + D.dir_off;
-  int n = 0;
-  if (i == 0) n += t[j];
-  if (i == D.nx - 1) n += t[D.ny + j];
-  if (j == 0) n += t[2 * D.ny + i];
-  if (j == D.ny - 1) n += t[2 * D.ny + D.nx + i];
-  return n;
+__device__ __forceinline__ int dirichlet_count(const HeatDesign& D, const uint8_t* dir, int i, int j) {
+  return heat::dirichlet_count(dir + D.dir_off, D.nx, D.ny, i, j);
 }
 
 template <typename T, int MODE>
@@ -93,17 +90,18 @@ __global__ __launch_bounds__(kBlock) void heat2d_kernel(HeatSweep<T> A) {
     const int lj = ty + r * (kBlock / TX) + 1;
     const long c = D.off + (long)j * D.nx + i;
     const T tc = sm.t[lj][li], kc = sm.k[lj][li];
-    T flux = T(0);   // sum over interior faces of k_f (T_c - T_nb)
-    if (i > 0) flux += T(0.5) * (kc + sm.k[lj][li - 1]) * (tc - sm.t[lj][li - 1]);
-    if (i < D.nx - 1) flux += T(0.5) * (kc + sm.k[lj][li + 1]) * (tc - sm.t[lj][li + 1]);
-    if (j > 0) flux += T(0.5) * (kc + sm.k[lj - 1][li]) * (tc - sm.t[lj - 1][li]);
-    if (j < D.ny - 1) flux += T(0.5) * (kc + sm.k[lj + 1][li]) * (tc - sm.t[lj + 1][li]);
+    const T kl = heat::face<T>(kc, sm.k[lj][li - 1], i > 0);
+    const T kr = heat::face<T>(kc, sm.k[lj][li + 1], i < D.nx - 1);
+    const T kd = heat::face<T>(kc, sm.k[lj - 1][li], j > 0);
+    const T ku = heat::face<T>(kc, sm.k[lj + 1][li], j < D.ny - 1);
     const int nd = (i == 0 || j == 0 || i == D.nx - 1 || j == D.ny - 1) ? dirichlet_count(D, A.dir, i, j) : 0;
-    const T rr = bb[r] - flux - T(2 * nd) * kc * tc;
+    const T rr = heat::residual<T>(bb[r], tc, kl, sm.t[lj][li - 1], kr, sm.t[lj][li + 1], kd, sm.t[lj - 1][li],
+                                   ku, sm.t[lj + 1][li], T(2 * nd) * kc);
     if (MODE == kSweep || MODE == kCheck) {
-      const T vn = ca * vv[r] + cc * rr;
+      T un = tc, vn = vv[r];
+      heat::update<T>(ca, cc, dt, rr, un, vn);
       A.v[c] = vn;
-      A.uout[c] = tc + dt * vn;
+      A.uout[c] = un;
     } else if (MODE == kResid) {
       A.v[c] = rr;
     } else {

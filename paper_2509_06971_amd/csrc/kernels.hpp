@@ -23,6 +23,8 @@ struct ElSweep {
   const T* uin;             // state read (ping)
   T* uout;                  // state written (pong); residual mode: unused
   T* v;                     // velocity, updated in place; residual mode: receives r
+  T* vout;                  // multi-sweep kernels: velocity written here (windows read
+                            // their neighbours' halo velocities, so no in-place update)
   const T* E;               // cell modulus
   const T* b;               // right-hand side per unknown (force units)
   const SolveState* st;     // coefficients and stop flag (sweep / check; refine: stop flag or nullptr)
@@ -84,6 +86,7 @@ struct HeatSweep {
   const T* uin;
   T* uout;
   T* v;
+  T* vout;                  // multi-sweep kernel: velocity output (see ElSweep)
   const T* k;
   const T* b;               // dense rhs or nullptr (uniform source)
   const HeatDesign* des;
@@ -97,6 +100,10 @@ struct HeatSweep {
 };
 template <typename T, int MODE>
 void launch_heat2d(const HeatSweep<T>& a, hipStream_t s);
+// K sweeps per launch on 64x32 windows; the work list holds the inner
+// (64-2K) x (32-2K) blocks.  Bit-identical to K one-sweep launches.
+template <typename T, int K, bool CHECK>
+void launch_heat2d_tb(const HeatSweep<T>& a, hipStream_t s);
 
 template <typename U, typename T>
 struct HeatAdjoint {
@@ -143,6 +150,7 @@ struct SetupArgs {
   double theta, dt_user, tol;
   int max_iter, check_every;
   int replay;
+  int adapt;
   int* ctl;                   // [0] = poll sequence, [1] = all_done
 };
 void launch_setup(const SetupArgs& a, hipStream_t s);
@@ -158,7 +166,16 @@ struct FinalizeArgs {
   PollRecord* ring;           // host-mapped ring
   int mode;                   // 0: check after the block's sweeps; 1: check before them (refinement)
   double div_factor;
+  const double* prq;          // adaptive damping: [ndes][rq_blocks][3] sums of u.u, u.F, u.r
+  int rq_blocks;
 };
+
+// Per-design sums of u.u, u.F and u.r over the state (FP64), for the Rayleigh
+// quotient of the adaptive damping.  F: dense load (double) or nullptr (uniform
+// source of the range).
+template <typename U, typename R>
+void launch_rq(const U* u, const R* r, const double* F, const StateRange* ranges, int ndes, int bpd,
+               double* prq, hipStream_t s);
 void launch_finalize(const FinalizeArgs& a, hipStream_t s);
 
 template <typename T>

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <functional>
+#include <map>
 #include <type_traits>
 #include <string>
 #include <algorithm>
@@ -46,8 +47,15 @@ petto_status fail(petto_status s, const char* fmt, ...) {
   } while (0)
 
 constexpr int kBpd = 256;          // material-kernel blocks per design
+constexpr int kRqBlocks = 64;      // Rayleigh-quotient blocks per design
 constexpr int kMaxOuter = 64;      // refinement: correction solves per call
 constexpr double kDivFactor = 1e4;
+
+struct TileList {            // heat work list for one sweeps-per-launch choice
+  HeatTile* tiles = nullptr;
+  int* tile0 = nullptr;      // [ndes + 1] per-design tile ranges
+  int ntile = 0;
+};
 
 struct GraphEntry {
   std::vector<const void*> key;
@@ -72,17 +80,21 @@ struct petto_ctx {
   HeatTile* d_tiles = nullptr;
   uint8_t* d_dir = nullptr;
   int* d_tile0 = nullptr;
-  int ntile = 0;                       // heat: work-list length; elastic: partial slots
+  int ntile = 0;                       // partial-sum slots (largest tiling)
+  std::map<int, TileList> heat_lists;  // heat work lists per sweeps-per-launch
   std::vector<HeatDesign> h_des;
   CellRange* d_ranges = nullptr;
   std::vector<CellRange> h_ranges;
   long* d_ncell = nullptr;
   double* d_fnorm = nullptr;
   double* d_h = nullptr;
+  StateRange* d_srange = nullptr;      // per-design state ranges (Rayleigh-quotient sums)
+  double* prq = nullptr;               // [nprob][kRqBlocks][3]
   std::vector<double> fnorm;
   double m0 = 1.0;
   // workspace
   void* ualt = nullptr;
+  void* valt = nullptr;                // velocity ping-pong partner of multi-sweep launches
   void* E = nullptr;
   double* E64 = nullptr;
   float* d32a = nullptr;
@@ -361,6 +373,10 @@ petto_status check_apt_params(const petto_ctx* c, const petto_apt_params* p) {
   if (p->replay_iters < 0 || (p->replay_iters % p->check_every) != 0)
     return fail(PETTO_ERR_INVALID, "replay_iters must be a nonnegative multiple of check_every");
   if (p->replay_iters == 0 && !(p->tol > 0.0)) return fail(PETTO_ERR_INVALID, "tol must be > 0");
+  if (p->adapt) {
+    if (p->dt > 0.0) return fail(PETTO_ERR_INVALID, "adapt needs the automatic step (dt <= 0)");
+    if (!(p->theta > 0.0)) return fail(PETTO_ERR_INVALID, "adapt needs theta > 0 (the damping floor)");
+  }
   if (p->refine) {
     if (c->prec != PETTO_FP32) return fail(PETTO_ERR_INVALID, "refine applies to FP32 contexts only");
     if (p->replay_iters) return fail(PETTO_ERR_INVALID, "replay_iters cannot be combined with refine");
@@ -373,7 +389,7 @@ petto_status check_apt_params(const petto_ctx* c, const petto_apt_params* p) {
 // Sweeps per launch for a block of nchk sweeps: the context's choice when the
 // block splits into an even number of launches of that size, else 1.
 int block_k(const petto_ctx* c, int nchk) {
-  if (c->physics != PETTO_ELASTIC || c->ndim != 2) return 1;
+  if (c->ndim != 2) return 1;
   const int k = c->blocking > 0 ? c->blocking : 1;
   return (k > 1 && nchk % (2 * k) == 0) ? k : 1;
 }
@@ -424,10 +440,13 @@ int elastic_sweeps(const petto_ctx* c, hipStream_t s, T* u, T* ualt, T* v, const
   a.partial = c->partial;
   const int k = block_k(c, nchk);
   const int nl = nchk / k;
+  T* valt = static_cast<T*>(c->valt);
   int nt = 0;
   for (int q = 0; q < nl; ++q) {
     a.uin = (q & 1) ? ualt : u;
     a.uout = (q & 1) ? u : ualt;
+    a.v = (k > 1 && (q & 1)) ? valt : v;
+    a.vout = (k > 1 && !(q & 1)) ? valt : v;
     const bool chk = check && q == nl - 1;
     if (c->ndim == 2) {
       if (k > 1) nt = chk ? launch_tb<T, true>(k, c->geom, a, s) : launch_tb<T, false>(k, c->geom, a, s);
@@ -439,26 +458,53 @@ int elastic_sweeps(const petto_ctx* c, hipStream_t s, T* u, T* ualt, T* v, const
   return nt;
 }
 
+template <typename T, bool CHECK>
+void launch_htb(int k, const HeatSweep<T>& a, hipStream_t s) {
+  switch (k) {
+    case 2: launch_heat2d_tb<T, 2, CHECK>(a, s); break;
+    case 4: launch_heat2d_tb<T, 4, CHECK>(a, s); break;
+    case 5: launch_heat2d_tb<T, 5, CHECK>(a, s); break;
+    case 8: if (std::is_same<T, float>::value) launch_heat2d_tb<float, 8, CHECK>(reinterpret_cast<const HeatSweep<float>&>(a), s); break;
+    case 10: if (std::is_same<T, float>::value) launch_heat2d_tb<float, 10, CHECK>(reinterpret_cast<const HeatSweep<float>&>(a), s); break;
+    default: break;
+  }
+}
+
+// nchk heat sweeps of every unconverged design; returns the work list the last
+// (checking) launch used, whose tile ranges the finalize kernel needs.
 template <typename T>
-void heat_sweeps(const petto_ctx* c, hipStream_t s, T* u, T* ualt, T* v, const T* k, const T* b,
-                 SolveState* st, int nchk, bool check = false) {
+const TileList* heat_sweeps(const petto_ctx* c, hipStream_t s, T* u, T* ualt, T* v, const T* k, const T* b,
+                            SolveState* st, int nchk, bool check = false) {
+  const int kk = block_k(c, nchk);
+  const TileList& L = c->heat_lists.at(kk);
   HeatSweep<T> a{};
   a.v = v;
   a.k = k;
   a.b = b;
   a.des = c->d_des;
-  a.tiles = c->d_tiles;
+  a.tiles = L.tiles;
   a.dir = c->d_dir;
   a.st = st;
   a.all_done = c->ctl + 1;
   a.partial = c->partial;
-  a.ntile = c->ntile;
-  for (int q = 0; q < nchk; ++q) {
+  a.ntile = L.ntile;
+  const int nl = nchk / kk;
+  T* valt = static_cast<T*>(c->valt);
+  for (int q = 0; q < nl; ++q) {
     a.uin = (q & 1) ? ualt : u;
     a.uout = (q & 1) ? u : ualt;
-    if (check && q == nchk - 1) launch_heat2d<T, kCheck>(a, s);
-    else launch_heat2d<T, kSweep>(a, s);
+    a.v = (kk > 1 && (q & 1)) ? valt : v;
+    a.vout = (kk > 1 && !(q & 1)) ? valt : v;
+    const bool chk = check && q == nl - 1;
+    if (kk == 1) {
+      if (chk) launch_heat2d<T, kCheck>(a, s);
+      else launch_heat2d<T, kSweep>(a, s);
+    } else {
+      if (chk) launch_htb<T, true>(kk, a, s);
+      else launch_htb<T, false>(kk, a, s);
+    }
   }
+  return &L;
 }
 
 int el_tiles_for(const petto_ctx* c, bool fp64) {
@@ -466,13 +512,17 @@ int el_tiles_for(const petto_ctx* c, bool fp64) {
   return el3d_tiles_prec(c->geom, fp64);   // 3D tiles depend on the kernel precision
 }
 
-// ntile: partial-sum slots the checking launch wrote (elastic; heat uses its list).
-void finalize(const petto_ctx* c, hipStream_t s, SolveState* st, int ntile, int mode) {
+// The partial sums the checking launch wrote: per-design ranges tile0 (heat
+// batches) or, for one design, slots [0, ntile).
+void finalize(const petto_ctx* c, hipStream_t s, SolveState* st, const int* tile0, int ntile, int mode,
+              bool adapt = false) {
   FinalizeArgs f{};
+  f.prq = adapt ? c->prq : nullptr;
+  f.rq_blocks = kRqBlocks;
   f.st = st;
   f.partial = c->partial;
-  f.tile0 = c->physics == PETTO_HEAT ? c->d_tile0 : nullptr;
-  f.ntile = c->physics == PETTO_HEAT ? c->ntile : ntile;
+  f.tile0 = tile0;
+  f.ntile = ntile;
   f.ndes = c->nprob;
   f.ncell = c->d_ncell;
   f.ctl = c->ctl;
@@ -495,6 +545,7 @@ petto_status material(petto_ctx* c, const void* phi, hipStream_t s, bool with64)
 petto_status setup(petto_ctx* c, hipStream_t s, SolveState* st, const petto_apt_params* ap, double tol, int replay,
                    int max_iter) {
   SetupArgs a{};
+  a.adapt = ap->adapt != 0;
   a.st = st;
   a.partial_max = c->partial_max;
   a.blocks_per_design = kBpd;
@@ -537,7 +588,7 @@ petto_status status_of(const std::vector<SolveState>& h) {
 // on the choice (all candidates are bit-identical).
 petto_status ensure_blocking(petto_ctx* c, hipStream_t s, int nchk) {
   if (c->blocking != 0) return PETTO_OK;
-  if (c->physics != PETTO_ELASTIC || c->ndim != 2 || c->prec != PETTO_FP32) {
+  if (c->ndim != 2 || c->prec != PETTO_FP32) {
     c->blocking = 1;
     return PETTO_OK;
   }
@@ -547,40 +598,37 @@ petto_status ensure_blocking(petto_ctx* c, hipStream_t s, int nchk) {
   float* v = static_cast<float*>(c->ualt);
   launch_fill<float>(u, c->nstate, 0.f, s);
   launch_fill<float>(v, c->nstate, 0.f, s);
-  ElSweep<float> a{};
-  a.v = v;
-  a.E = static_cast<const float*>(c->E);
-  a.b = c->b32;
-  a.st = c->st;
-  a.partial = c->partial;
   launch_fill<float>(c->b32, c->nstate, 0.f, s);
+  const float* E = static_cast<const float*>(c->E);
   const int cand[] = {1, 2, 4, 5, 8, 10};
   double best = 1e300;
   int best_k = 1;
+  const int saved = c->blocking;
   for (int k : cand) {
     if (nchk % (2 * k) != 0) continue;
+    c->blocking = k;
     const int reps = 40 / k < 4 ? 4 : 40 / k;
     auto run = [&](int n) {
-      for (int q = 0; q < n; ++q) {
-        a.uin = (q & 1) ? ua : u;
-        a.uout = (q & 1) ? u : ua;
-        if (k == 1) launch_el2d<float, kSweep>(c->geom, a, s);
-        else launch_tb<float, false>(k, c->geom, a, s);
+      if (c->physics == PETTO_ELASTIC) {
+        for (int q = 0; q < n; ++q) elastic_sweeps<float>(c, s, u, ua, v, E, c->b32, c->st, 2 * k);
+      } else {
+        for (int q = 0; q < n; ++q) heat_sweeps<float>(c, s, u, ua, v, E, nullptr, c->st, 2 * k);
       }
     };
-    run(2);
+    run(1);
     HIP_TRY(hipEventRecord(c->ev_beg[0], s));
     run(reps);
     HIP_TRY(hipEventRecord(c->ev_end[0], s));
     HIP_TRY(hipEventSynchronize(c->ev_end[0]));
     float ms = 0.f;
     HIP_TRY(hipEventElapsedTime(&ms, c->ev_beg[0], c->ev_end[0]));
-    const double per_sweep = ms / (double)(reps * k);
+    const double per_sweep = ms / (double)(reps * 2 * k);
     if (per_sweep < best) {
       best = per_sweep;
       best_k = k;
     }
   }
+  (void)saved;
   HIP_TRY(hipGetLastError());
   c->blocking = best_k;
   return PETTO_OK;
@@ -602,14 +650,46 @@ petto_status solve_plain(petto_ctx* c, const void* phi, void* u, void* v, const 
   const T* b = static_cast<const T*>(c->Ft);
   const int nchk = ap->check_every;
   if (std::is_same<T, float>::value) PETTO_TRY(ensure_blocking(c, s, nchk));
+  const bool adapt = ap->adapt != 0;
   std::function<void(hipStream_t)> body = [=](hipStream_t st) {
+    const int* tile0 = nullptr;
     int nt = 0;
-    if (c->physics == PETTO_ELASTIC) nt = elastic_sweeps<T>(c, st, uu, ua, vv, E, b, c->st, nchk, true);
-    else heat_sweeps<T>(c, st, uu, ua, vv, E, b, c->st, nchk, true);
-    finalize(c, st, c->st, nt, 0);
+    if (c->physics == PETTO_ELASTIC) {
+      nt = elastic_sweeps<T>(c, st, uu, ua, vv, E, b, c->st, nchk, true);
+    } else {
+      const TileList* L = heat_sweeps<T>(c, st, uu, ua, vv, E, b, c->st, nchk, true);
+      tile0 = L->tile0;
+      nt = L->ntile;
+    }
+    if (adapt) {
+      // residual of the block-boundary state into the free ping-pong buffer, then
+      // the Rayleigh-quotient sums
+      if (c->physics == PETTO_ELASTIC) {
+        ElSweep<T> a{};
+        a.uin = uu;
+        a.v = ua;
+        a.E = E;
+        a.b = b;
+        if (c->ndim == 2) launch_el2d<T, kResid>(c->geom, a, st);
+        else launch_el3d<T, kResid>(c->geom, a, st);
+      } else {
+        HeatSweep<T> a{};
+        a.uin = uu;
+        a.v = ua;
+        a.k = E;
+        a.b = b;
+        a.des = c->d_des;
+        a.tiles = c->heat_lists.at(1).tiles;
+        a.dir = c->d_dir;
+        a.ntile = c->heat_lists.at(1).ntile;
+        launch_heat2d<T, kResid>(a, st);
+      }
+      launch_rq<T, T>(uu, ua, c->F64, c->d_srange, c->nprob, kRqBlocks, c->prq, st);
+    }
+    finalize(c, st, c->st, tile0, nt, 0, adapt);
   };
   std::vector<const void*> key = {uu, ua, vv, E, b, (const void*)(long)nchk, (const void*)(long)sizeof(T),
-                                  (const void*)1, (const void*)(long)block_k(c, nchk)};
+                                  (const void*)1, (const void*)(long)block_k(c, nchk), (const void*)(long)adapt};
   PollRecord last{};
   PETTO_TRY(run_blocks(c, s, ap->use_graph != 0, key, body, nchk, &last));
   std::vector<SolveState> h;
@@ -622,6 +702,7 @@ petto_status solve_plain(petto_ctx* c, const void* phi, void* u, void* v, const 
       info[d].rel_res = h[d].rho;
       info[d].r_pde = h[d].r_pde;
       info[d].dt = h[d].dt;
+      info[d].theta = h[d].theta;
     }
   }
   return status_of(h);
@@ -647,6 +728,7 @@ petto_status solve_refine(petto_ctx* c, const void* phi, void* u, void* v, const
   const int nchk = ap->check_every;
   const float* E = static_cast<const float*>(c->E);
   const float* b = c->b32;
+  const bool adapt = ap->adapt != 0;
   std::function<void(hipStream_t)> body = [=](hipStream_t st) {
     launch_fold(u64, da, c->nstate, c->ctl + 1, st);
     if (c->physics == PETTO_ELASTIC) {
@@ -665,21 +747,23 @@ petto_status solve_refine(petto_ctx* c, const void* phi, void* u, void* v, const
       a.k = c->E64;
       a.b = c->F64;
       a.des = c->d_des;
-      a.tiles = c->d_tiles;
+      a.tiles = c->heat_lists.at(1).tiles;
       a.dir = c->d_dir;
       a.st = c->st;
       a.all_done = c->ctl + 1;
       a.partial = c->partial;
       a.b32 = c->b32;
-      a.ntile = c->ntile;
+      a.ntile = c->heat_lists.at(1).ntile;
       launch_heat2d<double, kRefine>(a, st);
     }
-    finalize(c, st, c->st, c->physics == PETTO_ELASTIC ? el_tiles_for(c, true) : 0, 1);
+    if (adapt) launch_rq<double, float>(u64, c->b32, c->F64, c->d_srange, c->nprob, kRqBlocks, c->prq, st);
+    if (c->physics == PETTO_ELASTIC) finalize(c, st, c->st, nullptr, el_tiles_for(c, true), 1, adapt);
+    else finalize(c, st, c->st, c->heat_lists.at(1).tile0, c->heat_lists.at(1).ntile, 1, adapt);
     if (c->physics == PETTO_ELASTIC) elastic_sweeps<float>(c, st, da, db, v32, E, b, c->st, nchk);
     else heat_sweeps<float>(c, st, da, db, v32, E, b, c->st, nchk);
   };
   std::vector<const void*> key = {u64, da, db, v32, E, b, (const void*)(long)nchk, (const void*)2,
-                                  (const void*)(long)block_k(c, nchk)};
+                                  (const void*)(long)block_k(c, nchk), (const void*)(long)adapt};
   PollRecord last{};
   PETTO_TRY(run_blocks(c, s, ap->use_graph != 0, key, body, nchk, &last));
   std::vector<SolveState> h;
@@ -692,13 +776,15 @@ petto_status solve_refine(petto_ctx* c, const void* phi, void* u, void* v, const
       info[d].rel_res = h[d].rho;
       info[d].r_pde = h[d].r_pde;
       info[d].dt = h[d].dt;
+      info[d].theta = h[d].theta;
     }
   }
   return status_of(h);
 }
 
+// Returns the partial-sum slots written (elastic; heat uses the design ranges).
 template <typename U, typename T>
-void adjoint_launch(petto_ctx* c, const void* phi, const void* u, const void* w, void* grad, hipStream_t s) {
+int adjoint_launch(petto_ctx* c, const void* phi, const void* u, const void* w, void* grad, hipStream_t s) {
   const petto_problem& p = c->probs[0];
   if (c->physics == PETTO_ELASTIC) {
     ElAdjoint<U, T> a{};
@@ -714,8 +800,7 @@ void adjoint_launch(petto_ctx* c, const void* phi, const void* u, const void* w,
     a.emin = p.emin;
     a.p = p.p;
     for (int m = 0; m < 3; ++m) a.ep[m] = p.e_phase[m];
-    if (c->ndim == 2) launch_el2d_adjoint<U, T>(c->geom, a, s);
-    else launch_el3d_adjoint<U, T>(c->geom, a, s);
+    return c->ndim == 2 ? launch_el2d_adjoint<U, T>(c->geom, a, s) : launch_el3d_adjoint<U, T>(c->geom, a, s);
   } else {
     HeatAdjoint<U, T> a{};
     a.u = static_cast<const U*>(u);
@@ -724,15 +809,16 @@ void adjoint_launch(petto_ctx* c, const void* phi, const void* u, const void* w,
     a.grad = static_cast<T*>(grad);
     a.F = c->F64;
     a.des = c->d_des;
-    a.tiles = c->d_tiles;
+    a.tiles = c->heat_lists.at(1).tiles;
     a.dir = c->d_dir;
     a.partial_fu = c->partial;
     a.partial_en = c->partial2;
     a.e0 = p.e0;
     a.emin = p.emin;
     a.p = p.p;
-    a.ntile = c->ntile;
+    a.ntile = c->heat_lists.at(1).ntile;
     launch_heat2d_adjoint<U, T>(a, s);
+    return 0;
   }
 }
 
@@ -927,12 +1013,33 @@ petto_status petto_create(const petto_problem* probs, int32_t nprob, int32_t pre
     c->ncell = soff;
     c->ntile = t0;
     c->m0 = 1.0;
-    // device copies
+    // device copies; work lists for one sweep per launch (64 x 8 tiles) and for
+    // every multi-sweep choice ((64-2K) x (32-2K) inner blocks)
     auto up = [&]() -> petto_status {
       PETTO_TRY(upload(c, &c->d_des, c->h_des));
       PETTO_TRY(upload(c, &c->d_tiles, tiles));
       PETTO_TRY(upload(c, &c->d_dir, dir));
       PETTO_TRY(upload(c, &c->d_tile0, tile0));
+      c->heat_lists[1] = TileList{c->d_tiles, c->d_tile0, t0};
+      std::vector<int> ks = {2, 4, 5};
+      if (prec == PETTO_FP32) ks.insert(ks.end(), {8, 10});
+      for (int k : ks) {
+        const int txi = 64 - 2 * k, tyi = 32 - 2 * k;
+        std::vector<HeatTile> tl;
+        std::vector<int> t0k;
+        for (int d = 0; d < nprob; ++d) {
+          t0k.push_back((int)tl.size());
+          for (int j0 = 0; j0 < probs[d].n[1]; j0 += tyi)
+            for (int i0 = 0; i0 < probs[d].n[0]; i0 += txi) tl.push_back({d, i0, j0, 0});
+        }
+        t0k.push_back((int)tl.size());
+        TileList L;
+        L.ntile = (int)tl.size();
+        PETTO_TRY(upload(c, &L.tiles, tl));
+        PETTO_TRY(upload(c, &L.tile0, t0k));
+        c->heat_lists[k] = L;
+        c->ntile = std::max(c->ntile, L.ntile);
+      }
       return PETTO_OK;
     };
     petto_status st = up();
@@ -965,7 +1072,15 @@ petto_status petto_create(const petto_problem* probs, int32_t nprob, int32_t pre
     PETTO_TRY(upload(c, &c->d_ncell, nc));
     PETTO_TRY(upload(c, &c->d_fnorm, c->fnorm));
     PETTO_TRY(upload(c, &c->d_h, hh));
+    std::vector<StateRange> sr;
+    if (c->physics == PETTO_ELASTIC) sr.push_back({0, c->nstate, 0.0});
+    else
+      for (int d = 0; d < nprob; ++d) sr.push_back({c->h_des[d].off, (long)c->h_des[d].nx * c->h_des[d].ny,
+                                                    c->h_des[d].fsrc});
+    PETTO_TRY(upload(c, &c->d_srange, sr));
+    PETTO_TRY(dalloc_t(c, &c->prq, (size_t)nprob * kRqBlocks * 3));
     PETTO_TRY(dalloc(c, &c->ualt, c->nstate * es));
+    PETTO_TRY(dalloc(c, &c->valt, c->nstate * es));
     PETTO_TRY(dalloc(c, &c->E, c->ncell * es));
     if (prec == PETTO_FP32) {
       PETTO_TRY(dalloc_t(c, &c->E64, c->ncell));
@@ -1095,9 +1210,9 @@ petto_status petto_residual(petto_ctx* ctx, const void* phi, const void* u, void
       a.k = static_cast<const T*>(ctx->E);
       a.b = static_cast<const T*>(ctx->Ft);
       a.des = ctx->d_des;
-      a.tiles = ctx->d_tiles;
+      a.tiles = ctx->heat_lists.at(1).tiles;
       a.dir = ctx->d_dir;
-      a.ntile = ctx->ntile;
+      a.ntile = ctx->heat_lists.at(1).ntile;
       launch_heat2d<T, kResid>(a, s);
     }
     HIP_TRY(hipGetLastError());
@@ -1115,16 +1230,9 @@ petto_status petto_adjoint(petto_ctx* ctx, const void* phi, const void* u, const
     return fail(PETTO_ERR_INVALID, "phi, u and grad_phi must be non-NULL");
   hipStream_t s = static_cast<hipStream_t>(stream);
   int nt = 0;
-  if (ctx->prec == PETTO_FP64) {
-    adjoint_launch<double, double>(ctx, phi, u, w, grad_phi, s);
-    nt = ctx->physics == PETTO_HEAT ? ctx->ntile : el_tiles_for(ctx, true);
-  } else if (state_fp64) {
-    adjoint_launch<double, float>(ctx, phi, u, w, grad_phi, s);
-    nt = ctx->physics == PETTO_HEAT ? ctx->ntile : el_tiles_for(ctx, true);
-  } else {
-    adjoint_launch<float, float>(ctx, phi, u, w, grad_phi, s);
-    nt = ctx->physics == PETTO_HEAT ? ctx->ntile : el_tiles_for(ctx, false);
-  }
+  if (ctx->prec == PETTO_FP64) nt = adjoint_launch<double, double>(ctx, phi, u, w, grad_phi, s);
+  else if (state_fp64) nt = adjoint_launch<double, float>(ctx, phi, u, w, grad_phi, s);
+  else nt = adjoint_launch<float, float>(ctx, phi, u, w, grad_phi, s);
   launch_dot_finalize(ctx->partial, ctx->partial2, ctx->physics == PETTO_HEAT ? ctx->d_tile0 : nullptr, nt,
                       ctx->nprob, compliance ? compliance : ctx->comp, s);
   HIP_TRY(hipGetLastError());

@@ -61,3 +61,36 @@ def test_refined_solve_same_for_every_blocking_and_autotune():
         assert it == outs[0][1]
         assert np.array_equal(u, outs[0][0])
     ctx.close()
+
+
+@pytest.mark.parametrize("prec,ks", [("fp32", (1, 2, 4, 5, 8, 10)), ("fp64", (1, 2, 5))])
+def test_heat_batch_blocking_bit_identical(prec, ks):
+    require_gpu()
+    probs, phis, _ = W.heat_batch_small()
+    announce(f"heat blocking {prec} ks={ks}")
+    dtype = torch.float64 if prec == "fp64" else torch.float32
+    rng = np.random.default_rng(2)
+    u0 = [rng.uniform(-1, 1, p.cell_shape()) * 1e-3 for p in probs]
+    if prec == "fp32":
+        u0 = [x.astype(np.float32).astype(np.float64) for x in u0]
+        phis = [x.astype(np.float32).astype(np.float64) for x in phis]
+    ctx = context(probs, prec)
+    phi_t = dev(np.concatenate([x.ravel() for x in phis]), dtype)
+    outs = {}
+    for k in ks:
+        ctx.set_blocking(k)
+        u = dev(np.concatenate([x.ravel() for x in u0]), dtype)
+        v = ctx.new_state()
+        st, info = ctx.solve(phi_t, u, v, theta=1.0, replay_iters=400, check_every=80)
+        outs[k] = (u.cpu().numpy().copy(), v.cpu().numpy().copy(), [x["rel_res"] for x in info])
+    ref = outs[ks[0]]
+    for k in ks[1:]:
+        assert np.array_equal(outs[k][0], ref[0]), k
+        assert np.array_equal(outs[k][1], ref[1]), k
+        assert outs[k][2] == pytest.approx(ref[2], rel=1e-12), k
+    got = ref[0]
+    for d, p in enumerate(probs):
+        o0, o1 = ctx.offset(d, 1), ctx.offset(d + 1, 1)
+        res, _ = design.solve(phis[d], p, u0=u0[d], params=design.AptParams(theta=1.0, check_every=80), n_iter=400)
+        assert rel_l2(got[o0:o1].reshape(p.cell_shape()), res.u) < (1e-12 if prec == "fp64" else 2e-5), d
+    ctx.close()

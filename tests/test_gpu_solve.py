@@ -151,3 +151,46 @@ def test_two_runs_bit_identical():
         outs.append(u.cpu().numpy())
     assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
     ctx.close()
+
+
+def test_adaptive_damping_matches_oracle():
+    """Damping re-chosen at every check from the Rayleigh quotient of the state:
+    the FP64 GPU solve stops on the oracle's sweep with the oracle's state, from
+    rest and warm-started after a design change."""
+    require_gpu()
+    prob = W.cantilever2d(64, 32)
+    announce("adaptive damping fp64")
+    ctx = context(prob, "fp64")
+    phi0 = W.initial_phi(prob)
+    phi1 = W.random_phi(prob, 4, 0.3, 1.0)
+    u = ctx.new_state()
+    v = ctx.new_state()
+    uo = np.zeros(prob.u_shape())
+    for phi in (phi0, phi1):
+        st, info = ctx.solve(dev(phi, torch.float64), u, v, theta=1.0, tol=1e-6, check_every=100, adapt=True)
+        res, _ = design.solve(phi, prob, u0=uo, params=design.AptParams(theta=1.0, tol=1e-6, check_every=100,
+                                                                       adapt=True))
+        assert res.converged and st == L.OK
+        assert info[0]["iters"] == res.iters
+        assert info[0]["theta"] == pytest.approx(res.theta, rel=1e-9)
+        assert rel_l2(host(u, prob.u_shape()), res.u) < 1e-10
+        uo = res.u
+    ctx.close()
+
+
+def test_adaptive_damping_refined_fp32():
+    require_gpu()
+    prob = W.cantilever2d(128, 64)
+    announce("adaptive damping fp32 refined")
+    phi = W.random_phi(prob, 5, 0.3, 1.0).astype(np.float32).astype(np.float64)
+    ctx = context(prob, "fp32")
+    u = ctx.new_state(torch.float64)
+    v = ctx.new_state()
+    st, info = ctx.solve(dev(phi, torch.float32), u, v, theta=1.0, tol=1e-7, refine=True, adapt=True)
+    st1, info1 = ctx.solve(dev(phi, torch.float32), ctx.new_state(torch.float64), v, theta=1.0, tol=1e-7,
+                           refine=True)
+    assert st == L.OK and info[0]["iters"] < info1[0]["iters"]
+    E = design.material(phi, prob)
+    ud = assembly.direct_solve(design.stiffness(E, prob), design.load_vector(prob), prob)
+    assert rel_l2(host(u, prob.u_shape()), ud) < 1e-4
+    ctx.close()

@@ -99,3 +99,27 @@ def test_stop_rule_reports_checked_residual():
     # replaying the same count reproduces the same state
     res2, _ = design.solve(phi, prob, params=design.AptParams(tol=1e-3, check_every=10), n_iter=res.iters)
     np.testing.assert_array_equal(res.u, res2.u)
+
+
+def test_adapted_theta_single_unknown():
+    """For one unknown K = kappa the Rayleigh quotient is kappa exactly, so the
+    critically damping choice is theta = 1 / (4 kappa) (floored)."""
+    kappa, F = 0.02, 1.0
+    u = np.array([3.0])
+    r = F - kappa * u
+    assert apt.adapted_theta(u, r, np.array([F]), 1.0, 1.0) == pytest.approx(1.0 / (4 * kappa))
+    assert apt.adapted_theta(u, r, np.array([F]), 1.0, 100.0) == pytest.approx(100.0)
+    assert apt.adapted_theta(np.zeros(1), r, np.array([F]), 1.0, 1.0) is None
+
+
+def test_adaptive_damping_reaches_direct_solution_faster():
+    prob = W.cantilever2d(16, 8)
+    phi = W.initial_phi(prob)
+    plain, _ = design.solve(phi, prob, params=design.AptParams(theta=1.0, tol=1e-9, check_every=20))
+    fast, _ = design.solve(phi, prob, params=design.AptParams(theta=1.0, tol=1e-9, check_every=20, adapt=True))
+    assert plain.converged and fast.converged
+    assert fast.iters < plain.iters / 2
+    assert fast.theta > 1.0
+    E = design.material(phi, prob)
+    ud = assembly.direct_solve(design.stiffness(E, prob), design.load_vector(prob), prob)
+    assert np.linalg.norm(fast.u - ud) / np.linalg.norm(ud) < 1e-7
