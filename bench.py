@@ -75,9 +75,10 @@ def cpu_baseline(prob, phi0, sweeps):
                       f"{prob.n[0]}x{prob.n[1]} grid (FP64 NumPy/SciPy, single-threaded sparse products)"}
 
 
-# Algorithmic bytes per cell and sweep of the other FP32 sweep kernels (state and
-# velocity read + written, material read; the heat batch has a uniform source).
-BYTES_PER_CELL = {"heat_batch64": 20, "cantilever3d_128x64x64": 52, "multimaterial3d_256x128x128": 52}
+# Algorithmic bytes per cell and sweep of the other FP32 sweep kernels: state and
+# velocity read + written, material read, and (3D) the load read; the heat batch
+# has a uniform source.
+BYTES_PER_CELL = {"heat_batch64": 20, "cantilever3d_128x64x64": 64, "multimaterial3d_256x128x128": 64}
 
 
 def sweep_leg(args):

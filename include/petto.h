@@ -218,11 +218,25 @@ petto_status petto_set_timing(petto_ctx *ctx, int32_t on);
  * launch; k = 0 (default for FP32 contexts): time the candidates on the first
  * solve and keep the fastest.  A block of check_every sweeps uses k only when
  * check_every is a multiple of 2k, else one sweep per launch.  FP64 contexts
- * default to 1; 3D contexts stream along z with one sweep per launch. */
+ * default to 1; 3D contexts stream along z with one sweep per launch (tiling:
+ * petto_set_tile3d). */
 petto_status petto_set_blocking(petto_ctx *ctx, int32_t k);
 
 /* The sweeps per launch in use (0: not chosen yet). */
 int32_t petto_blocking(const petto_ctx *ctx);
+
+/* Tiling of the 3D elastic sweeps (streamed along z, Eqs. 3.6 and 3.12 in 3D):
+ * t = 1: columns of 64 x 8 positions (FP64: 64 x 4) through 8 layers, the fewest
+ * halo bytes; t = 2: columns of 64 x 4 positions through 4 layers, more
+ * workgroups for small grids; t = 0: choose as at creation (t = 1 when it gives
+ * at least two workgroups per compute unit, else t = 2).  Results are
+ * bit-identical for both tilings except the order of the FP64 residual-norm sum.
+ * Errors: PETTO_ERR_INVALID for other values or a context that is not 3D elastic.
+ * Cached launch graphs are dropped. */
+petto_status petto_set_tile3d(petto_ctx *ctx, int32_t t);
+
+/* The 3D tiling in use (1 or 2; 0 for a NULL context). */
+int32_t petto_tile3d(const petto_ctx *ctx);
 
 /* Message of the last failure on the calling thread ("" if none). */
 const char *petto_last_error(void);

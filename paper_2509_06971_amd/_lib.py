@@ -95,6 +95,8 @@ def load(path: str = LIB_PATH):
         "petto_set_timing": (st, [vp, C.c_int32]),
         "petto_set_blocking": (st, [vp, C.c_int32]),
         "petto_blocking": (C.c_int32, [vp]),
+        "petto_set_tile3d": (st, [vp, C.c_int32]),
+        "petto_tile3d": (C.c_int32, [vp]),
         "petto_last_error": (C.c_char_p, []),
         "petto_version": (C.c_char_p, []),
     }

@@ -172,6 +172,13 @@ class Context:
     def blocking(self):
         return int(self.lib.petto_blocking(self.h))
 
+    def set_tile3d(self, t):
+        """Tiling of the 3D elastic sweeps: 1 large columns, 2 small, 0 automatic."""
+        L.check(self.lib.petto_set_tile3d(self.h, int(t)))
+
+    def tile3d(self):
+        return int(self.lib.petto_tile3d(self.h))
+
     def set_timing(self, on=True):
         L.check(self.lib.petto_set_timing(self.h, int(bool(on))))
 

@@ -16,7 +16,7 @@ namespace petto {
 namespace {
 
 constexpr int TX = 64;
-constexpr int LX = TX + 2;
+constexpr int LX = TX + 3;   // halo column on each side, plus the x = nx face column
 
 template <typename T, int TY>
 struct Sm3 {
@@ -54,20 +54,53 @@ __device__ __forceinline__ T face3(const ElGeom& g, const T* __restrict__ u, int
   return sgn * u[(long)a * g.plane + ((long)id[2] * g.py + id[1]) * g.px + id[0]];
 }
 
+// Staging of one z-layer: each thread fetches its share of the (TY+2) x (TX+2)
+// halo plane into registers (ahead of time) and later stores it to LDS.
 template <typename T, int TY>
-__device__ __forceinline__ void load_plane(const ElGeom& g, const T* __restrict__ u, const T* __restrict__ E,
-                                           int i0, int j0, int k, int buf, Sm3<T, TY>& sm) {
+struct Plane {
+  static constexpr int LY = TY + 2;
+  static constexpr int NE = (LY * LX + TX * TY - 1) / (TX * TY);
+  T v[NE][4];   // u_x, u_y, u_z, modulus
+};
+
+template <typename T, int TY>
+__device__ __forceinline__ void fetch_plane(const ElGeom& g, const T* __restrict__ u, const T* __restrict__ E,
+                                            int i0, int j0, int k, Plane<T, TY>& P) {
   constexpr int LY = TY + 2;
-  for (int q = threadIdx.x; q < LY * LX; q += TX * TY) {
+#pragma unroll
+  for (int e = 0; e < Plane<T, TY>::NE; ++e) {
+    const int q = threadIdx.x + e * TX * TY;
+    P.v[e][0] = P.v[e][1] = P.v[e][2] = P.v[e][3] = T(0);
+    if (q >= LY * LX) continue;
     const int b = q / LX, a = q - b * LX;
     const int i = i0 - 1 + a, j = j0 - 1 + b;
-    sm.u[buf][0][b][a] = face3<T>(g, u, 0, i, j, k);
-    sm.u[buf][1][b][a] = face3<T>(g, u, 1, i, j, k);
-    sm.u[buf][2][b][a] = face3<T>(g, u, 2, i, j, k);
-    T ev = T(0);
-    if (E != nullptr && i >= 0 && i < g.nx && j >= 0 && j < g.ny && k >= 0 && k < g.nz)
-      ev = E[((long)k * g.ny + j) * g.nx + i];
-    sm.e[buf][b][a] = ev;
+    if (i >= 0 && i < g.nx && j >= 0 && j < g.ny && k >= 0 && k < g.nz) {
+      // interior: every component's indices are in range, no ghosts
+      const long p = ((long)k * g.py + j) * g.px + i;
+      P.v[e][0] = u[p];
+      P.v[e][1] = u[g.plane + p];
+      P.v[e][2] = u[2 * g.plane + p];
+      P.v[e][3] = E != nullptr ? E[((long)k * g.ny + j) * g.nx + i] : T(0);
+    } else {
+      P.v[e][0] = face3<T>(g, u, 0, i, j, k);
+      P.v[e][1] = face3<T>(g, u, 1, i, j, k);
+      P.v[e][2] = face3<T>(g, u, 2, i, j, k);
+    }
+  }
+}
+
+template <typename T, int TY>
+__device__ __forceinline__ void store_plane(const Plane<T, TY>& P, int buf, Sm3<T, TY>& sm) {
+  constexpr int LY = TY + 2;
+#pragma unroll
+  for (int e = 0; e < Plane<T, TY>::NE; ++e) {
+    const int q = threadIdx.x + e * TX * TY;
+    if (q >= LY * LX) continue;
+    const int b = q / LX, a = q - b * LX;
+    sm.u[buf][0][b][a] = P.v[e][0];
+    sm.u[buf][1][b][a] = P.v[e][1];
+    sm.u[buf][2][b][a] = P.v[e][2];
+    sm.e[buf][b][a] = P.v[e][3];
   }
 }
 
@@ -126,6 +159,36 @@ __device__ __forceinline__ T own_szz(const Sm3<T, TY>& sm, int a, int b, int cur
   return szz;
 }
 
+// Result of one unknown: the damped update (sweep modes), the residual (kResid)
+// or its FP32 rounding (kRefine); r^2 accumulated on checking modes.
+template <typename T, int MODE>
+__device__ __forceinline__ void finish(const ElSweep<T>& A, long gi, bool fix, T r, T un, T vn, T ca, T cc, T dt,
+                                       double& acc) {
+  r = fix ? T(0) : r;
+  if (MODE == kSweep || MODE == kCheck) {
+    if (!fix) el3d::update<T>(ca, cc, dt, r, un, vn);
+    A.v[gi] = vn;
+    A.uout[gi] = un;
+  } else if (MODE == kResid) {
+    A.v[gi] = r;
+  } else {
+    A.b32[gi] = (float)r;
+  }
+  if (MODE == kCheck || MODE == kRefine) acc += (double)r * (double)r;
+}
+
+// Padding slot of a component array: written as zero.
+template <typename T, int MODE>
+__device__ __forceinline__ void zero_slot(const ElSweep<T>& A, long gi) {
+  if (MODE == kSweep || MODE == kCheck) A.uout[gi] = T(0);
+  else if (MODE == kResid) A.v[gi] = T(0);
+  else A.b32[gi] = 0.f;
+}
+
+// Tiling: x-tiles of TX positions cover i < nx, and the tile ending at i = nx - 1
+// also takes the face column i = nx (only u_x lives there) through TY of its
+// threads; y-tiles of TY rows cover j <= ny; z-tiles of KZ layers, the last one
+// running through layer nz.
 template <typename T, int TY, int KZ, int MODE>
 __global__ __launch_bounds__(TX * TY) void el3d_stream_kernel(ElGeom g, ElSweep<T> A, int tiles_x, int tiles_y,
                                                               int ntiles) {
@@ -133,10 +196,12 @@ __global__ __launch_bounds__(TX * TY) void el3d_stream_kernel(ElGeom g, ElSweep<
     if (A.st->done) return;
   }
   constexpr int LY = TY + 2;
+  constexpr int XA = TX + 1;             // LDS column of the face column i = i0 + TX
   __shared__ Sm3<T, TY> sm;
   const int tile = xcd_tile(blockIdx.x, ntiles);
-  const int tz = tile / (tiles_x * tiles_y);
-  const int trem = tile - tz * tiles_x * tiles_y;
+  const int txy = tiles_x * tiles_y;
+  const int tz = tile / txy;
+  const int trem = tile - tz * txy;
   const int tyi = trem / tiles_x, txi = trem - tyi * tiles_x;
   const int i0 = txi * TX, j0 = tyi * TY, k0 = tz * KZ;
   const int a = 1 + (int)(threadIdx.x % TX), b = 1 + (int)(threadIdx.x / TX);
@@ -151,19 +216,29 @@ __global__ __launch_bounds__(TX * TY) void el3d_stream_kernel(ElGeom g, ElSweep<
     cc = T(A.st->c);
     dt = T(A.st->dt);
   }
+  // face-column duty: thread t < TY takes row t of the column i = nx
+  const int ej = j0 + (int)threadIdx.x;
+  const bool xface = i0 + TX == nx && (int)threadIdx.x < TY && ej <= ny;
+  const bool xfok = xface && ej < ny;
+  const int kend = (tz == ntiles / txy - 1) ? nz + 1 : k0 + KZ;
   // prologue: planes k0-1 (into buffer 1) and k0 (buffer 0); xz/yz shear at z = k0
-  // into buffer 0; sigma_zz of the own cell at k0-1
-  load_plane<T, TY>(g, A.uin, A.E, i0, j0, k0 - 1, 1, sm);
-  load_plane<T, TY>(g, A.uin, A.E, i0, j0, k0, 0, sm);
+  // into buffer 0; sigma_zz of the own cell at k0-1; plane k0+1 fetched ahead
+  Plane<T, TY> P;
+  fetch_plane<T, TY>(g, A.uin, A.E, i0, j0, k0 - 1, P);
+  store_plane<T, TY>(P, 1, sm);
+  fetch_plane<T, TY>(g, A.uin, A.E, i0, j0, k0, P);
+  store_plane<T, TY>(P, 0, sm);
   __syncthreads();
+  fetch_plane<T, TY>(g, A.uin, A.E, i0, j0, k0 + 1, P);
   xz_yz_planes<T, TY>(g, i0, j0, k0, 1, 0, 0, rh, mu0, sm);
   T szz_prev = own_szz<T, TY>(sm, a, b, 1, 0, rh, lam0, mu0);
   __syncthreads();
   double acc = 0.0;
   int cur = 0;
-  const int kend = (k0 + KZ < nz + 1) ? k0 + KZ : nz + 1;
   for (int k = k0; k < kend; ++k) {
     const int up = cur ^ 1;
+    // plane k+1 into LDS (its buffer was last read before the previous barrier)
+    store_plane<T, TY>(P, up, sm);
     // own velocity / right-hand side of layer k
     const long p = ((long)k * g.py + j) * g.px + i;
     const bool in = i <= nx && j <= ny;
@@ -175,12 +250,22 @@ __global__ __launch_bounds__(TX * TY) void el3d_stream_kernel(ElGeom g, ElSweep<
       if ((MODE == kSweep || MODE == kCheck) && ok[c]) vv[c] = A.v[c * pl + p];
       bb[c] = ok[c] ? A.b[c * pl + p] : T(0);
     }
-    load_plane<T, TY>(g, A.uin, A.E, i0, j0, k + 1, up, sm);
+    const long pe = ((long)k * g.py + ej) * g.px + nx;
+    const bool xok = xfok && k < nz;
+    T vxe = T(0), bxe = T(0);
+    if (xok) {
+      if (MODE == kSweep || MODE == kCheck) vxe = A.v[pe];
+      bxe = A.b[pe];
+    }
     __syncthreads();
+    // fetch plane k+2 while this layer computes
+    if (k + 1 < kend) fetch_plane<T, TY>(g, A.uin, A.E, i0, j0, k + 2, P);
+    const T uo[3] = {sm.u[cur][0][b][a], sm.u[cur][1][b][a], sm.u[cur][2][b][a]};
+    const T uxe = xok ? sm.u[cur][0][1 + threadIdx.x][XA] : T(0);
     // normal stresses (cells of layer k) and xy shear (layer k)
     for (int q = threadIdx.x; q < LY * LX; q += TX * TY) {
       const int bb2 = q / LX, aa = q - bb2 * LX;
-      T sxx = T(0), syy = T(0), txy = T(0);
+      T sxx = T(0), syy = T(0), txy_ = T(0);
       if (aa + 1 < LX && bb2 + 1 < LY) {
         const T e = sm.e[cur][bb2][aa];
         const T exx = (sm.u[cur][0][bb2][aa + 1] - sm.u[cur][0][bb2][aa]) * rh;
@@ -199,16 +284,16 @@ __global__ __launch_bounds__(TX * TY) void el3d_stream_kernel(ElGeom g, ElSweep<
                                           sm.e[cur][bb2][aa - 1], sm.e[cur][bb2][aa], act, on);
         const T gam = el3d::shear_strain<T>(sm.u[cur][0][bb2][aa], sm.u[cur][0][bb2 - 1][aa], sm.u[cur][1][bb2][aa],
                                             sm.u[cur][1][bb2][aa - 1], rh);
-        txy = m * gam;
+        txy_ = m * gam;
       }
       sm.sxx[bb2][aa] = sxx;
       sm.syy[bb2][aa] = syy;
-      sm.txy[bb2][aa] = txy;
+      sm.txy[bb2][aa] = txy_;
     }
     xz_yz_planes<T, TY>(g, i0, j0, k + 1, cur, up, up, rh, mu0, sm);
     const T szz_cur = own_szz<T, TY>(sm, a, b, cur, up, rh, lam0, mu0);
     __syncthreads();
-    // residuals and update of the own position at layer k
+    // residuals and update of the own position at layer k (reads stress planes only)
     if (in) {
       T rr[3];
       rr[0] = el3d::residual<T>(bb[0], h2, sm.sxx[b][a], sm.sxx[b][a - 1], sm.txy[b + 1][a], sm.txy[b][a],
@@ -221,31 +306,33 @@ __global__ __launch_bounds__(TX * TY) void el3d_stream_kernel(ElGeom g, ElSweep<
       for (int c = 0; c < 3; ++c) {
         const long gi = c * pl + p;
         if (!ok[c]) {
-          if (MODE == kSweep || MODE == kCheck) A.uout[gi] = T(0);
-          else if (MODE == kResid) A.v[gi] = T(0);
-          else A.b32[gi] = 0.f;
+          zero_slot<T, MODE>(A, gi);
           continue;
         }
         const int own = c == 0 ? i : c == 1 ? j : k;
         const int nown = c == 0 ? nx : c == 1 ? ny : nz;
         const bool fix = (own == 0 && g.fixn[2 * c]) || (own == nown && g.fixn[2 * c + 1]) || pinned3s(g.pins, gi);
-        const T r = fix ? T(0) : rr[c];
-        T uo = sm.u[cur][c][b][a], vn = vv[c];
-        if (MODE == kSweep || MODE == kCheck) {
-          if (!fix) el3d::update<T>(ca, cc, dt, r, uo, vn);
-          A.v[gi] = vn;
-          A.uout[gi] = uo;
-        } else if (MODE == kResid) {
-          A.v[gi] = r;
-        } else {
-          A.b32[gi] = (float)r;
-        }
-        if (MODE == kCheck || MODE == kRefine) acc += (double)r * (double)r;
+        finish<T, MODE>(A, gi, fix, rr[c], uo[c], vv[c], ca, cc, dt, acc);
       }
+    }
+    // the face column i = nx: u_x only (u_y, u_z slots are padding)
+    if (xface) {
+      const int eb = 1 + (int)threadIdx.x;
+      if (xok) {
+        const T r = el3d::residual<T>(bxe, h2, sm.sxx[eb][XA], sm.sxx[eb][XA - 1], sm.txy[eb + 1][XA],
+                                      sm.txy[eb][XA], sm.txz[up][eb][XA], sm.txz[cur][eb][XA]);
+        const bool fix = g.fixn[1] || pinned3s(g.pins, pe);
+        finish<T, MODE>(A, pe, fix, r, uxe, vxe, ca, cc, dt, acc);
+      } else {
+        zero_slot<T, MODE>(A, pe);
+      }
+      zero_slot<T, MODE>(A, pl + pe);
+      zero_slot<T, MODE>(A, 2 * pl + pe);
     }
     szz_prev = szz_cur;
     cur = up;
-    __syncthreads();
+    // the next store writes the plane read before the barrier above, and the
+    // stress planes read here are rewritten only after the next barrier
   }
   if (MODE == kCheck || MODE == kRefine) {
     const double s = block_sum(acc, sm.red);
@@ -253,39 +340,61 @@ __global__ __launch_bounds__(TX * TY) void el3d_stream_kernel(ElGeom g, ElSweep<
   }
 }
 
-template <typename T> struct Cfg3;
-template <> struct Cfg3<float> { static constexpr int TY = 8, KZ = 8; };
-template <> struct Cfg3<double> { static constexpr int TY = 4, KZ = 8; };
+// Two tilings per precision: columns of 64 x TY positions streamed through KZ
+// layers.  The large one moves the fewest halo bytes; the small one gives
+// small grids enough workgroups to fill the chip.
+template <typename T, int V> struct Cfg3;
+template <> struct Cfg3<float, 1> { static constexpr int TY = 8, KZ = 8; };
+template <> struct Cfg3<float, 2> { static constexpr int TY = 4, KZ = 4; };
+template <> struct Cfg3<double, 1> { static constexpr int TY = 4, KZ = 8; };
+template <> struct Cfg3<double, 2> { static constexpr int TY = 4, KZ = 4; };
 
-template <typename T>
+template <typename T, int V>
 void tiles_s(const ElGeom& g, int& tx, int& ty, int& tz) {
-  tx = (g.nx + 1 + TX - 1) / TX;
-  ty = (g.ny + 1 + Cfg3<T>::TY - 1) / Cfg3<T>::TY;
-  tz = (g.nz + 1 + Cfg3<T>::KZ - 1) / Cfg3<T>::KZ;
+  tx = (g.nx + TX - 1) / TX;
+  ty = (g.ny + 1 + Cfg3<T, V>::TY - 1) / Cfg3<T, V>::TY;
+  tz = (g.nz + Cfg3<T, V>::KZ - 1) / Cfg3<T, V>::KZ;
+}
+
+template <typename T, int V>
+int count_s(const ElGeom& g) {
+  int a, b, c;
+  tiles_s<T, V>(g, a, b, c);
+  return a * b * c;
+}
+
+template <typename T, int V, int MODE>
+int launch_v(const ElGeom& g, const ElSweep<T>& a, hipStream_t s) {
+  int tx, ty, tz;
+  tiles_s<T, V>(g, tx, ty, tz);
+  const int nt = tx * ty * tz;
+  constexpr int TY = Cfg3<T, V>::TY, KZ = Cfg3<T, V>::KZ;
+  hipLaunchKernelGGL((el3d_stream_kernel<T, TY, KZ, MODE>), dim3(nt), dim3(TX * TY), 0, s, g, a, tx, ty, nt);
+  return nt;
 }
 
 }  // namespace
 
 int el3d_tiles_prec(const ElGeom& g, bool fp64) {
-  int a, b, c;
-  if (fp64) tiles_s<double>(g, a, b, c);
-  else tiles_s<float>(g, a, b, c);
-  return a * b * c;
+  if (fp64) return g.tile3d == 2 ? count_s<double, 2>(g) : count_s<double, 1>(g);
+  return g.tile3d == 2 ? count_s<float, 2>(g) : count_s<float, 1>(g);
 }
 
 int el3d_tiles(const ElGeom& g) {
-  const int n1 = el3d_tiles_prec(g, false), n2 = el3d_tiles_prec(g, true);
-  return n1 > n2 ? n1 : n2;
+  const int c[4] = {count_s<float, 1>(g), count_s<float, 2>(g), count_s<double, 1>(g), count_s<double, 2>(g)};
+  int m = 0;
+  for (int x : c) m = x > m ? x : m;
+  return m;
+}
+
+int el3d_choose_tiling(const ElGeom& g, bool fp64, int ncu) {
+  const int large = fp64 ? count_s<double, 1>(g) : count_s<float, 1>(g);
+  return large >= 2 * ncu ? 1 : 2;
 }
 
 template <typename T, int MODE>
 int launch_el3d(const ElGeom& g, const ElSweep<T>& a, hipStream_t s) {
-  int tx, ty, tz;
-  tiles_s<T>(g, tx, ty, tz);
-  const int nt = tx * ty * tz;
-  constexpr int TY = Cfg3<T>::TY, KZ = Cfg3<T>::KZ;
-  hipLaunchKernelGGL((el3d_stream_kernel<T, TY, KZ, MODE>), dim3(nt), dim3(TX * TY), 0, s, g, a, tx, ty, nt);
-  return nt;
+  return g.tile3d == 2 ? launch_v<T, 2, MODE>(g, a, s) : launch_v<T, 1, MODE>(g, a, s);
 }
 
 template int launch_el3d<float, kSweep>(const ElGeom&, const ElSweep<float>&, hipStream_t);

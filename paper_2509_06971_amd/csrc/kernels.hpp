@@ -16,6 +16,7 @@ struct ElGeom {
   int clamp[6];             // side is clamped: tangential unknowns reflect, edges active
   int fixn[6];              // side holds the normal unknown at zero (clamped or roller)
   const uint32_t* pins;     // extra Dirichlet unknowns as a bitmask, or nullptr
+  int tile3d;               // 3D sweep tiling: 1 large columns, 2 small columns
 };
 
 template <typename T>
@@ -38,13 +39,16 @@ int launch_el2d(const ElGeom& g, const ElSweep<T>& a, hipStream_t s);
 template <typename T, int MODE>
 int launch_el3d(const ElGeom& g, const ElSweep<T>& a, hipStream_t s);
 int el2d_tiles(const ElGeom& g);
-int el3d_tiles(const ElGeom& g);   // the larger tile count of the two precisions
+int el3d_tiles(const ElGeom& g);   // the largest tile count of every precision and tiling
 // K sweeps per launch on an LDS window (K in {2, 4, 5, 8, 10}); bit-identical to K
 // launches of the one-sweep kernel.  CHECK: the last sweep also sums r^2.
 template <typename T, int K, bool CHECK>
 int launch_el2d_tb(const ElGeom& g, const ElSweep<T>& a, hipStream_t s);
 int el2d_tb_tiles(const ElGeom& g, int K);   // 0 for an unsupported K
-int el3d_tiles_prec(const ElGeom& g, bool fp64);
+int el3d_tiles_prec(const ElGeom& g, bool fp64);   // for the tiling g.tile3d
+// Tiling for a grid: the large one when it gives at least two workgroups per
+// compute unit, else the small one.
+int el3d_choose_tiling(const ElGeom& g, bool fp64, int ncu);
 
 // Sensitivity: per cell g = -dE/dphi * B(w,u)/E-free form, plus dot(F,u) and 2 Pi(u)
 // partial sums per tile.

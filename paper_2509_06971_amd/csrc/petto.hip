@@ -117,6 +117,7 @@ struct petto_ctx {
   bool events = false;
   std::vector<GraphEntry> graphs;
   int blocking = 0;                    // sweeps per launch (2D elastic); 0: tune on first solve
+  int ncu = 256;                       // compute units of the device (3D tiling choice)
   bool timing = false;
   double timed_ms = 0.0;
   int64_t timed_sweeps = 0;
@@ -1062,6 +1063,13 @@ petto_status petto_create(const petto_problem* probs, int32_t nprob, int32_t pre
     }
     if (any_pin) PETTO_TRY(upload(c, &c->pins, pin_words));
     c->geom.pins = c->pins;
+    c->geom.tile3d = 1;
+    if (c->physics == PETTO_ELASTIC && c->ndim == 3) {
+      int dev = 0;
+      HIP_TRY(hipGetDevice(&dev));
+      HIP_TRY(hipDeviceGetAttribute(&c->ncu, hipDeviceAttributeMultiprocessorCount, dev));
+      c->geom.tile3d = el3d_choose_tiling(c->geom, prec == PETTO_FP64, c->ncu);
+    }
     std::vector<long> nc;
     std::vector<double> hh;
     for (const auto& r : c->h_ranges) {
@@ -1170,6 +1178,20 @@ petto_status petto_set_blocking(petto_ctx* ctx, int32_t k) {
 }
 
 int32_t petto_blocking(const petto_ctx* ctx) { return ctx ? ctx->blocking : 0; }
+
+petto_status petto_set_tile3d(petto_ctx* ctx, int32_t t) {
+  g_err.clear();
+  if (ctx == nullptr) return fail(PETTO_ERR_INVALID, "ctx is NULL");
+  if (ctx->physics != PETTO_ELASTIC || ctx->ndim != 3)
+    return fail(PETTO_ERR_INVALID, "the 3D tiling applies to 3D elastic contexts");
+  if (t < 0 || t > 2) return fail(PETTO_ERR_INVALID, "unsupported 3D tiling %d", t);
+  if (t == 0) t = el3d_choose_tiling(ctx->geom, ctx->prec == PETTO_FP64, ctx->ncu);
+  ctx->geom.tile3d = t;
+  destroy_graphs(ctx);
+  return PETTO_OK;
+}
+
+int32_t petto_tile3d(const petto_ctx* ctx) { return ctx ? ctx->geom.tile3d : 0; }
 
 petto_status petto_apt_solve(petto_ctx* ctx, const void* phi, void* u, void* v, const petto_apt_params* params,
                              void* stream, petto_solve_info* info) {

@@ -15,8 +15,14 @@ TOL_FP32 = 2e-6
 
 def _elastic_cases():
     return [("mixed2d", lambda: mixed_elastic(2)), ("mixed3d", lambda: mixed_elastic(3)),
+            ("mixed3d64", lambda: mixed_elastic(3, 1)),
             ("cant2d", lambda: W.cantilever2d(64, 32)), ("cant3d", lambda: W.cantilever3d(20, 8, 6)),
             ("multi3d", lambda: W.multimaterial3d(24, 10, 8))]
+
+
+def _tilings(prob):
+    """3D contexts: both sweep tilings; 2D: the default."""
+    return [1, 2] if prob.ndim == 3 else [None]
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
@@ -32,15 +38,19 @@ def test_elastic_residual_parity(name, make, prec):
         phi = phi.astype(np.float32).astype(np.float64)
         u = u.astype(np.float32).astype(np.float64)
     ctx = context(prob, prec)
-    r = ctx.new_state()
-    ctx.residual(dev(phi, dtype), dev(u, dtype), r)
-    torch.cuda.synchronize()
-    got = host(r, prob.u_shape())
     E = elastic.modulus(phi, prob)
     want = elastic.residual(u, E, prob, design.load_vector(prob))
     scale = np.abs(elastic.internal_force(np.abs(u), E, prob)).max() + np.abs(want).max()
-    err = np.abs(got - want).max() / scale
-    assert err < (TOL_FP64 if prec == "fp64" else TOL_FP32), err
+    for t in _tilings(prob):
+        if t is not None:
+            ctx.set_tile3d(t)
+        r = ctx.new_state()
+        r.fill_(7.0)    # padding slots must come back as zero
+        ctx.residual(dev(phi, dtype), dev(u, dtype), r)
+        torch.cuda.synchronize()
+        got = host(r, prob.u_shape())
+        err = np.abs(got - want).max() / scale
+        assert err < (TOL_FP64 if prec == "fp64" else TOL_FP32), (t, err)
     ctx.close()
 
 
@@ -73,12 +83,18 @@ def test_heat_batch_residual_parity(prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("name,make", _elastic_cases()[:2] + [("cant2d", lambda: W.cantilever2d(64, 32))])
+@pytest.mark.parametrize("name,make", _elastic_cases()[:3] + [("cant2d", lambda: W.cantilever2d(64, 32))])
 def test_sweeps_parity(name, make, prec):
-    """200 damped-wave sweeps from a random state equal the oracle's sweeps."""
+    """200 damped-wave sweeps from a random state equal the oracle's sweeps (3D:
+    with both sweep tilings)."""
     require_gpu()
     prob = make()
-    announce(f"sweeps {name} {prec}")
+    for t in _tilings(prob):
+        _sweeps_case(name, prob, prec, t)
+
+
+def _sweeps_case(name, prob, prec, tiling):
+    announce(f"sweeps {name} {prec} tiling={tiling}")
     phi = W.random_phi(prob, 6, 0.2, 1.0)
     u0 = W.random_u(prob, 7, scale=1e-2)
     dtype = torch.float64 if prec == "fp64" else torch.float32
@@ -86,6 +102,9 @@ def test_sweeps_parity(name, make, prec):
         phi = phi.astype(np.float32).astype(np.float64)
         u0 = u0.astype(np.float32).astype(np.float64)
     ctx = context(prob, prec)
+    if tiling is not None:
+        ctx.set_tile3d(tiling)
+        assert ctx.tile3d() == tiling
     u = dev(u0, dtype)
     v = ctx.new_state()
     for use_graph in (True, False):
