@@ -238,6 +238,16 @@ petto_status petto_set_tile3d(petto_ctx *ctx, int32_t t);
 /* The 3D tiling in use (1 or 2; 0 for a NULL context). */
 int32_t petto_tile3d(const petto_ctx *ctx);
 
+/* Time the context's dominant sweep kernel (the relaxation launch of Eq. 3.12 /
+ * the heat analogue, with the current sweeps per launch and tiling): `launches`
+ * (2..100000, rounded up to even) back-to-back launches, without checks, on
+ * workspace buffers (zero state; the caller's buffers are untouched) with the
+ * step coefficients of the last solve, bracketed by two HIP events on `stream`.
+ * Writes the mean milliseconds per launch and the sweeps each launch performs.
+ * Blocks until done.  FP32 contexts only (PETTO_ERR_UNSUPPORTED otherwise). */
+petto_status petto_time_sweeps(petto_ctx *ctx, int32_t launches, void *stream, double *ms_per_launch,
+                               int32_t *sweeps_per_launch);
+
 /* Message of the last failure on the calling thread ("" if none). */
 const char *petto_last_error(void);
 

@@ -96,6 +96,7 @@ def load(path: str = LIB_PATH):
         "petto_set_blocking": (st, [vp, C.c_int32]),
         "petto_blocking": (C.c_int32, [vp]),
         "petto_set_tile3d": (st, [vp, C.c_int32]),
+        "petto_time_sweeps": (st, [vp, C.c_int32, vp, C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
         "petto_tile3d": (C.c_int32, [vp]),
         "petto_last_error": (C.c_char_p, []),
         "petto_version": (C.c_char_p, []),

@@ -179,6 +179,14 @@ class Context:
     def tile3d(self):
         return int(self.lib.petto_tile3d(self.h))
 
+    def time_sweeps(self, launches=200, stream=None):
+        """Mean milliseconds per launch of the dominant sweep kernel and the sweeps
+        per launch, from HIP events around back-to-back launches on `stream`."""
+        ms = C.c_double()
+        k = C.c_int32()
+        L.check(self.lib.petto_time_sweeps(self.h, int(launches), _stream(stream), C.byref(ms), C.byref(k)))
+        return ms.value, k.value
+
     def set_timing(self, on=True):
         L.check(self.lib.petto_set_timing(self.h, int(bool(on))))
 

@@ -118,6 +118,7 @@ struct petto_ctx {
   std::vector<GraphEntry> graphs;
   int blocking = 0;                    // sweeps per launch (2D elastic); 0: tune on first solve
   int ncu = 256;                       // compute units of the device (3D tiling choice)
+  SolveState* st_t = nullptr;          // running copy of st for kernel timing (done = 0)
   bool timing = false;
   double timed_ms = 0.0;
   int64_t timed_sweeps = 0;
@@ -475,7 +476,7 @@ void launch_htb(int k, const HeatSweep<T>& a, hipStream_t s) {
 // (checking) launch used, whose tile ranges the finalize kernel needs.
 template <typename T>
 const TileList* heat_sweeps(const petto_ctx* c, hipStream_t s, T* u, T* ualt, T* v, const T* k, const T* b,
-                            SolveState* st, int nchk, bool check = false) {
+                            SolveState* st, int nchk, bool check = false, int* all_done = nullptr) {
   const int kk = block_k(c, nchk);
   const TileList& L = c->heat_lists.at(kk);
   HeatSweep<T> a{};
@@ -486,7 +487,7 @@ const TileList* heat_sweeps(const petto_ctx* c, hipStream_t s, T* u, T* ualt, T*
   a.tiles = L.tiles;
   a.dir = c->d_dir;
   a.st = st;
-  a.all_done = c->ctl + 1;
+  a.all_done = all_done != nullptr ? all_done : c->ctl + 1;
   a.partial = c->partial;
   a.ntile = L.ntile;
   const int nl = nchk / kk;
@@ -1178,6 +1179,49 @@ petto_status petto_set_blocking(petto_ctx* ctx, int32_t k) {
 }
 
 int32_t petto_blocking(const petto_ctx* ctx) { return ctx ? ctx->blocking : 0; }
+
+petto_status petto_time_sweeps(petto_ctx* ctx, int32_t launches, void* stream, double* ms_per_launch,
+                               int32_t* sweeps_per_launch) {
+  g_err.clear();
+  if (ctx == nullptr || ms_per_launch == nullptr || sweeps_per_launch == nullptr)
+    return fail(PETTO_ERR_INVALID, "ctx and outputs must not be NULL");
+  if (launches < 2 || launches > 100000) return fail(PETTO_ERR_INVALID, "launches must be in [2, 100000]");
+  if (ctx->prec != PETTO_FP32) return fail(PETTO_ERR_UNSUPPORTED, "sweep timing is for FP32 contexts");
+  petto_ctx* c = ctx;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  PETTO_TRY(ensure_events(c));
+  if (c->st_t == nullptr) PETTO_TRY(dalloc_t(c, &c->st_t, c->nprob));
+  // the coefficients of the last solve, with the stop flags cleared
+  std::vector<SolveState> hs(c->nprob);
+  HIP_TRY(hipStreamSynchronize(s));
+  HIP_TRY(hipMemcpy(hs.data(), c->st, c->nprob * sizeof(SolveState), hipMemcpyDeviceToHost));
+  for (auto& x : hs) x.done = 0;
+  HIP_TRY(hipMemcpy(c->st_t, hs.data(), c->nprob * sizeof(SolveState), hipMemcpyHostToDevice));
+  float* u = c->d32a;
+  float* ua = c->d32b;
+  float* v = static_cast<float*>(c->ualt);
+  launch_fill<float>(u, c->nstate, 0.f, s);
+  launch_fill<float>(v, c->nstate, 0.f, s);
+  launch_fill<float>(c->b32, c->nstate, 0.f, s);
+  const float* E = static_cast<const float*>(c->E);
+  const int k = c->physics == PETTO_ELASTIC && c->ndim == 3 ? 1 : (c->blocking > 0 ? c->blocking : 1);
+  const int n = launches + (launches & 1);           // even: the state ends where it began
+  auto run = [&](int nl) {
+    if (c->physics == PETTO_ELASTIC) elastic_sweeps<float>(c, s, u, ua, v, E, c->b32, c->st_t, nl * k);
+    else heat_sweeps<float>(c, s, u, ua, v, E, nullptr, c->st_t, nl * k, false, c->ctl + 2);
+  };
+  run(2);
+  HIP_TRY(hipEventRecord(c->ev_beg[0], s));
+  run(n);
+  HIP_TRY(hipEventRecord(c->ev_end[0], s));
+  HIP_TRY(hipEventSynchronize(c->ev_end[0]));
+  HIP_TRY(hipGetLastError());
+  float ms = 0.f;
+  HIP_TRY(hipEventElapsedTime(&ms, c->ev_beg[0], c->ev_end[0]));
+  *ms_per_launch = ms / (double)n;
+  *sweeps_per_launch = k;
+  return PETTO_OK;
+}
 
 petto_status petto_set_tile3d(petto_ctx* ctx, int32_t t) {
   g_err.clear();
