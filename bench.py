@@ -43,7 +43,7 @@ def parse():
     ap.add_argument("--ny", type=int, default=512)
     ap.add_argument("--theta", type=float, default=1.0)
     ap.add_argument("--tol", type=float, default=1e-6)
-    ap.add_argument("--cpu-sweeps", type=int, default=100)
+    ap.add_argument("--cpu-sweeps", type=int, default=1000)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-timing", action="store_true", help="skip the library's sweep-block events")
     ap.add_argument("--workload", default="cantilever2d",
@@ -66,13 +66,15 @@ def cpu_baseline(prob, phi0, sweeps):
 
     t0 = time.perf_counter()
     res, _ = design.solve(phi0, prob, params=design.AptParams(theta=1.0, check_every=100), n_iter=sweeps)
+    t1 = time.perf_counter()
     g = design.sensitivity(res.u, phi0, prob)
     design.phase_update(phi0, g, prob)
     dt = time.perf_counter() - t0
     cores = len(os.sched_getaffinity(0))
     value = prob.ncell * sweeps / dt
     return {"value": value, "unit": "cell-updates/s", "cores": 1, "cores_available": cores, "kind": "oracle",
-            "seconds": round(dt, 3),
+            "seconds": round(dt, 3), "sweep_seconds": (t1 - t0) / sweeps,
+            "sensitivity_and_phase_seconds": dt - (t1 - t0),
             "sample": f"{sweeps} sweeps from rest + 1 sensitivity + 1 phase update on the full "
                       f"{prob.n[0]}x{prob.n[1]} grid (FP64 NumPy/SciPy, single-threaded sparse products)"}
 
@@ -83,7 +85,38 @@ def cpu_baseline(prob, phi0, sweeps):
 BYTES_PER_CELL = {"heat_batch64": 20, "cantilever3d_128x64x64": 64, "multimaterial3d_256x128x128": 64}
 
 
-def kernel_roofline(ctx, bytes_per_sweep, family, launches=200):
+# Sources whose text decides each kernel family's memory traffic: a recorded
+# counter measurement applies only while they are unchanged.
+KERNEL_SOURCES = {"el2d": ["el2d_tb.hip", "el2d.hip", "el2d_ops.hpp"],
+                  "heat": ["heat2d_tb.hip", "heat2d.hip", "heat_ops.hpp"],
+                  "el3d": ["el3d_stream.hip", "el3d_ops.hpp"]}
+
+
+def source_digest(family):
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[family]:
+        with open(os.path.join(ROOT, "paper_2509_06971_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(family, name, workload):
+    """HBM bytes per launch from the FETCH_SIZE / WRITE_SIZE counter runs recorded
+    in profiles/traffic.json (calibrated by a plain copy), or None when there is
+    no record for this kernel and workload or its sources changed since."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as fh:
+            rec = json.load(fh).get(f"{name} @ {workload}")
+    except (OSError, ValueError):
+        return None
+    if not rec or rec.get("source_digest") != source_digest(family):
+        return None
+    return rec["fetch_kib"] * 1024 * rec["fetch_factor"] + rec["write_kib"] * 1024 * rec["write_factor"]
+
+
+def kernel_roofline(ctx, bytes_per_sweep, family, workload, launches=200):
     """Roofline of the dominant kernel: algorithmic bytes per launch (bytes per
     sweep x sweeps per launch) over its mean launch duration, from HIP events
     around back-to-back launches on the library's stream."""
@@ -93,10 +126,12 @@ def kernel_roofline(ctx, bytes_per_sweep, family, launches=200):
     elif family == "heat":
         name = f"heat2d_tb_kernel<float, {k}, false>" if k > 1 else "heat2d_kernel<float, 0>"
     else:
-        name = "el3d_stream_kernel<float, TY, KZ, 0>"
+        ty, kz = (8, 8) if ctx.tile3d() == 1 else (4, 4)
+        name = f"el3d_stream_kernel<float, {ty}, {kz}, 0>"
     achieved = bytes_per_sweep * k / (ms * 1e-3) / 1e9
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": name, "sweeps_per_launch": k,
+            "frac": achieved / HBM_PEAK_GBS, "traffic": recorded_traffic(family, name, workload),
+            "traffic_unit": "HBM bytes per launch", "kernel": name, "sweeps_per_launch": k,
             "launch_us": ms * 1e3, "bytes_per_launch": bytes_per_sweep * k, "timed_launches": launches}
 
 
@@ -131,7 +166,7 @@ def sweep_leg(args):
     ms, n = ctx.last_sweep_ms()
     bpc = BYTES_PER_CELL[args.workload]
     family = "heat" if args.workload.startswith("heat") else ("el3d" if "3d" in args.workload else "el2d")
-    roof = kernel_roofline(ctx, bpc * ncell, family)
+    roof = kernel_roofline(ctx, bpc * ncell, family, args.workload)
     roof["bytes_per_cell"] = bpc
     roof["block_sweep_us"] = ms * 1e3
     roof["block_achieved"] = bpc * ncell / (ms * 1e-3) / 1e9
@@ -179,12 +214,22 @@ def ttd_leg(args):
             st, si, pi, _ = ctx.step(phi, u, v, g, vol_frac=prob.vol_frac, compliance=comp, apt=apt)
             sweeps += si[0]["iters"]
             hist.append(si[0]["iters"])
+            print(f"[ttd] {mode} step {s + 1}/{args.ttd_steps}: {si[0]['iters']} sweeps, "
+                  f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         res[mode] = {"seconds": wall, "sweeps": sweeps, "compliance": comp[0].item(),
                      "energy2": comp[1].item(), "sweeps_per_step": hist,
                      "phi_final": phi.double().cpu().numpy()}
         ctx.close()
+    # the oracle on the host, timed on a bounded sample and extrapolated to the
+    # FP64 leg's recorded sweep counts (labelled as an extrapolation)
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(prob, phi0, args.cpu_sweeps)
+        cpu["extrapolated_seconds"] = (cpu["sweep_seconds"] * res["fp64"]["sweeps"] +
+                                       cpu["sensitivity_and_phase_seconds"] * args.ttd_steps)
+        cpu["note"] = "extrapolated from the timed sample and the FP64 leg's sweep counts"
     d_phi = float(np.abs(res["fp32"]["phi_final"] - res["fp64"]["phi_final"]).max())
     for m in res:
         res[m].pop("phi_final")
@@ -194,7 +239,7 @@ def ttd_leg(args):
         "fp32_refined_graph": res["fp32"], "fp64_plain": res["fp64"],
         "speedup": res["fp64"]["seconds"] / res["fp32"]["seconds"],
         "rel_compliance_diff": abs(res["fp32"]["compliance"] - res["fp64"]["compliance"]) /
-        res["fp64"]["compliance"], "max_design_diff": d_phi}
+        res["fp64"]["compliance"], "max_design_diff": d_phi, "cpu_oracle": cpu}
     print(json.dumps(out))
 
 
@@ -269,7 +314,7 @@ def main():
                    "compliance": comp[0].item()},
     }
     bytes_per_sweep = BYTES_PER_CELL_2D_FP32 * ncell
-    out["roofline"] = kernel_roofline(ctx, bytes_per_sweep, "el2d")
+    out["roofline"] = kernel_roofline(ctx, bytes_per_sweep, "el2d", f"cantilever2d_{args.nx}x{args.ny}")
     if sweeps_timed > 0:
         # whole sweep blocks as the solver ran them (sweep launches plus the
         # per-check FP64 residual, fold and finalize kernels), from the library's

@@ -37,6 +37,76 @@ __device__ __forceinline__ bool pinned_tb(const uint32_t* pins, long k) {
   return pins != nullptr && ((pins[k >> 5] >> (k & 31)) & 1u);
 }
 
+// K sweeps on the staged window.  Sweep k only forms the stresses of rows
+// [k, EY-k) and updates rows [k+1, EY-k-1): the values outside lie beyond the
+// dependency cone of the written inner rows [K, EY-K), so skipping them leaves
+// those rows unchanged (a row is one wave, so the skip is wave-uniform).  FAST:
+// the window is inside the grid with no pins (no ghosts, every unknown free).
+template <typename T, int K, bool CHECK, bool FAST>
+__device__ __forceinline__ void tb_sweeps(const ElGeom& g, TbSmem<T>& sm, T (&ux)[PPT], T (&uy)[PPT], T (&vx)[PPT],
+                                          T (&vy)[PPT], const T (&bx)[PPT], const T (&by)[PPT], const T (&lam)[PPT],
+                                          const T (&mu2)[PPT], const T (&mue)[PPT], const T (&fx)[PPT],
+                                          const T (&fy)[PPT], int i, int li, int lw, int c, int je, T rh, T h, T ca,
+                                          T cc, T dt, double& acc) {
+  const int nx = g.nx, ny = g.ny;
+  // reflected-ghost multipliers of clamped sides (0 on other sides), applied on the
+  // first / last row and column of the grid
+  const T gb = g.clamp[2] ? T(-1) : T(0), gt = g.clamp[3] ? T(-1) : T(0);
+  const T gl = g.clamp[0] ? T(-1) : T(0), gr = g.clamp[1] ? T(-1) : T(0);
+  for (int k = 0; k < K; ++k) {
+    // (B) stresses of the cell and the vertex at every position of rows [k, EY-k)
+#pragma unroll
+    for (int s = 0; s < PPT; ++s) {
+      const int lj = lw + s * RSTEP, j = je + lj, r = lj + 1;
+      if (lj < k || lj >= EY - k) continue;
+      const T uxs = ux[s], uys = uy[s];
+      const T ux_r = sm.dx[r][c + 1];
+      const T uy_u = sm.dy[r + 1][c];
+      const T ux_dn = sm.dx[r - 1][c];
+      const T uy_lf = sm.dy[r][c - 1];
+      T ux_below = ux_dn, uy_left = uy_lf, ux_here = uxs, uy_here = uys;
+      if (!FAST) {
+        // reflected ghosts of clamped sides, as the one-sweep kernel stages them
+        ux_below = j == 0 ? gb * uxs : ux_dn;
+        uy_left = i == 0 ? gl * uys : uy_lf;
+        ux_here = j == ny ? gt * ux_dn : uxs;
+        uy_here = i == nx ? gr * uy_lf : uys;
+      }
+      const T exx = (ux_r - uxs) * rh;
+      const T eyy = (uy_u - uys) * rh;
+      el2d::normal_stress<T>(lam[s], mu2[s], exx, eyy, sm.sxx[r][c], sm.syy[r][c]);
+      sm.tau[r][c] = mue[s] * el2d::shear_strain<T>(ux_here, ux_below, uy_here, uy_left, rh);
+    }
+    __syncthreads();
+    // (C) residuals and the damped update of every free unknown of rows [k+1, EY-k-1)
+#pragma unroll
+    for (int s = 0; s < PPT; ++s) {
+      const int lj = lw + s * RSTEP, r = lj + 1;
+      if (lj < k + 1 || lj >= EY - k - 1) continue;
+      const T t0 = sm.tau[r][c];
+      const T rx = el2d::residual<T>(bx[s], h, sm.sxx[r][c], sm.sxx[r][c - 1], sm.tau[r + 1][c], t0);
+      const T ry = el2d::residual<T>(by[s], h, sm.syy[r][c], sm.syy[r - 1][c], sm.tau[r][c + 1], t0);
+      T ux2 = ux[s], vx2 = vx[s], uy2 = uy[s], vy2 = vy[s];
+      el2d::update<T>(ca, cc, dt, rx, ux2, vx2);
+      el2d::update<T>(ca, cc, dt, ry, uy2, vy2);
+      const bool frx = FAST || fx[s] != T(0), fry = FAST || fy[s] != T(0);
+      ux[s] = frx ? ux2 : ux[s];
+      vx[s] = frx ? vx2 : vx[s];
+      uy[s] = fry ? uy2 : uy[s];
+      vy[s] = fry ? vy2 : vy[s];
+      if (CHECK && k == K - 1) {
+        const bool inner = li >= K && li < EX - K && lj >= K && lj < EY - K;
+        const double rx2 = (inner && frx) ? (double)rx * (double)rx : 0.0;
+        const double ry2 = (inner && fry) ? (double)ry * (double)ry : 0.0;
+        acc += rx2 + ry2;
+      }
+      sm.dx[r][c] = ux[s];
+      sm.dy[r][c] = uy[s];
+    }
+    __syncthreads();
+  }
+}
+
 // Window position (li, lj) lives at LDS [lj + 1][li + 1]; the pad ring stays zero,
 // so neighbour reads need no guards (edge results are outside the written inner
 // region anyway).
@@ -49,7 +119,8 @@ __global__ __launch_bounds__(NT) void el2d_tb_kernel(ElGeom g, ElSweep<T> A, int
   const int tile = xcd_tile(blockIdx.x, ntiles);
   const int tyi = tile / tiles_x, txi = tile - tyi * tiles_x;
   const int ie = txi * TXI - K, je = tyi * TYI - K;     // window origin
-  const int li = threadIdx.x % EX, lw = threadIdx.x / EX;
+  // one window row per wave: the row index is wave-uniform (scalar branches)
+  const int li = threadIdx.x % EX, lw = __builtin_amdgcn_readfirstlane(threadIdx.x / EX);
   const int nx = g.nx, ny = g.ny, px = g.px;
   const long pl = g.plane;
   const int i = ie + li;
@@ -115,57 +186,16 @@ __global__ __launch_bounds__(NT) void el2d_tb_kernel(ElGeom g, ElSweep<T> A, int
 
   const T rh = T(1.0 / g.h), h = T(g.h);
   const T ca = T(A.st->a), cc = T(A.st->c), dt = T(A.st->dt);
-  // reflected-ghost multipliers of clamped sides (0 on other sides), applied on the
-  // first / last row and column of the grid
-  const T gb = g.clamp[2] ? T(-1) : T(0), gt = g.clamp[3] ? T(-1) : T(0);
-  const T gl = g.clamp[0] ? T(-1) : T(0), gr = g.clamp[1] ? T(-1) : T(0);
+  // A window that lies strictly inside the grid and holds no pinned unknown has
+  // no ghosts and no fixed unknowns: its sweeps skip those selects.
+  const bool inner_window = ie >= 1 && je >= 1 && ie + EX <= nx && je + EY <= ny && g.pins == nullptr;
   double acc = 0.0;
-  for (int k = 0; k < K; ++k) {
-    // (B) stresses of the cell and the vertex at every position of the window
-#pragma unroll
-    for (int s = 0; s < PPT; ++s) {
-      const int lj = lw + s * RSTEP, j = je + lj, r = lj + 1;
-      const T uxs = ux[s], uys = uy[s];
-      const T ux_r = sm.dx[r][c + 1];
-      const T uy_u = sm.dy[r + 1][c];
-      const T ux_dn = sm.dx[r - 1][c];
-      const T uy_lf = sm.dy[r][c - 1];
-      // reflected ghosts of clamped sides, as the one-sweep kernel stages them
-      const T ux_below = j == 0 ? gb * uxs : ux_dn;
-      const T uy_left = i == 0 ? gl * uys : uy_lf;
-      const T ux_here = j == ny ? gt * ux_dn : uxs;
-      const T uy_here = i == nx ? gr * uy_lf : uys;
-      const T exx = (ux_r - uxs) * rh;
-      const T eyy = (uy_u - uys) * rh;
-      el2d::normal_stress<T>(lam[s], mu2[s], exx, eyy, sm.sxx[r][c], sm.syy[r][c]);
-      sm.tau[r][c] = mue[s] * el2d::shear_strain<T>(ux_here, ux_below, uy_here, uy_left, rh);
-    }
-    __syncthreads();
-    // (C) residuals and the damped update of every free unknown
-#pragma unroll
-    for (int s = 0; s < PPT; ++s) {
-      const int lj = lw + s * RSTEP, r = lj + 1;
-      const T t0 = sm.tau[r][c];
-      const T rx = el2d::residual<T>(bx[s], h, sm.sxx[r][c], sm.sxx[r][c - 1], sm.tau[r + 1][c], t0);
-      const T ry = el2d::residual<T>(by[s], h, sm.syy[r][c], sm.syy[r - 1][c], sm.tau[r][c + 1], t0);
-      T ux2 = ux[s], vx2 = vx[s], uy2 = uy[s], vy2 = vy[s];
-      el2d::update<T>(ca, cc, dt, rx, ux2, vx2);
-      el2d::update<T>(ca, cc, dt, ry, uy2, vy2);
-      const bool frx = fx[s] != T(0), fry = fy[s] != T(0);
-      ux[s] = frx ? ux2 : ux[s];
-      vx[s] = frx ? vx2 : vx[s];
-      uy[s] = fry ? uy2 : uy[s];
-      vy[s] = fry ? vy2 : vy[s];
-      if (CHECK && k == K - 1) {
-        const bool inner = li >= K && li < EX - K && lj >= K && lj < EY - K;
-        const double rx2 = (inner && frx) ? (double)rx * (double)rx : 0.0;
-        const double ry2 = (inner && fry) ? (double)ry * (double)ry : 0.0;
-        acc += rx2 + ry2;
-      }
-      sm.dx[r][c] = ux[s];
-      sm.dy[r][c] = uy[s];
-    }
-    __syncthreads();
+  if (inner_window) {
+    tb_sweeps<T, K, CHECK, true>(g, sm, ux, uy, vx, vy, bx, by, lam, mu2, mue, fx, fy, i, li, lw, c, je, rh, h, ca, cc,
+                                 dt, acc);
+  } else {
+    tb_sweeps<T, K, CHECK, false>(g, sm, ux, uy, vx, vy, bx, by, lam, mu2, mue, fx, fy, i, li, lw, c, je, rh, h, ca,
+                                  cc, dt, acc);
   }
   // write back the inner positions (padding slots of the grid get zero)
 #pragma unroll

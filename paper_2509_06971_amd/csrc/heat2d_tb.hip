@@ -29,6 +29,38 @@ struct HTb {
   double red[NT / kWave];
 };
 
+// K sweeps on the staged window.  Sweep k updates rows [k+1, EY-k-1) only: the
+// rows outside lie beyond the dependency cone of the written rows [K, EY-K)
+// (one row per wave, so the skip is wave-uniform), and rows a sweep skips are
+// never read by a row it updates.  FAST: every window position is a cell.
+template <typename T, int K, bool CHECK, bool FAST>
+__device__ __forceinline__ void heat_tb_sweeps(HTb<T>& sm, T (&tt)[PPT], T (&vv)[PPT], const T (&bb)[PPT],
+                                               const T (&kl)[PPT], const T (&kr)[PPT], const T (&kd)[PPT],
+                                               const T (&ku)[PPT], const T (&dd)[PPT], const bool (&cell)[PPT],
+                                               int li, int lw, int c, T ca, T cc, T dt, double& acc) {
+  for (int k = 0; k < K; ++k) {
+    const int cur = k & 1;
+#pragma unroll
+    for (int s = 0; s < PPT; ++s) {
+      const int lj = lw + s * RSTEP, r = lj + 1;
+      if (lj < k + 1 || lj >= EY - k - 1) continue;
+      const T rr = heat::residual<T>(bb[s], tt[s], kl[s], sm.t[cur][r][c - 1], kr[s], sm.t[cur][r][c + 1], kd[s],
+                                     sm.t[cur][r - 1][c], ku[s], sm.t[cur][r + 1][c], dd[s]);
+      T un = tt[s], vn = vv[s];
+      heat::update<T>(ca, cc, dt, rr, un, vn);
+      const bool live = FAST || cell[s];
+      tt[s] = live ? un : tt[s];
+      vv[s] = live ? vn : vv[s];
+      if (CHECK && k == K - 1) {
+        const bool inner = li >= K && li < EX - K && lj >= K && lj < EY - K && live;
+        acc += inner ? (double)rr * (double)rr : 0.0;
+      }
+      sm.t[cur ^ 1][r][c] = tt[s];
+    }
+    __syncthreads();
+  }
+}
+
 template <typename T, int K, bool CHECK>
 __global__ __launch_bounds__(NT) void heat2d_tb_kernel(HeatSweep<T> A) {
   if (*A.all_done) return;
@@ -39,7 +71,8 @@ __global__ __launch_bounds__(NT) void heat2d_tb_kernel(HeatSweep<T> A) {
   const HeatDesign D = A.des[tl.design];
   __shared__ HTb<T> sm;
   const int ie = tl.i0 - K, je = tl.j0 - K;
-  const int li = threadIdx.x % EX, lw = threadIdx.x / EX;
+  // one window row per wave: the row index is wave-uniform (scalar branches)
+  const int li = threadIdx.x % EX, lw = __builtin_amdgcn_readfirstlane(threadIdx.x / EX);
   const int c = li + 1, i = ie + li;
   const uint8_t* dir = A.dir + D.dir_off;
 
@@ -81,26 +114,11 @@ __global__ __launch_bounds__(NT) void heat2d_tb_kernel(HeatSweep<T> A) {
     ku[s] = heat::face<T>(kc[s], sm.k[r + 1][c], j < D.ny - 1);
   }
   const T ca = T(st->a), cc = T(st->c), dt = T(st->dt);
+  // a window inside its design: every position is a cell (no selects)
+  const bool inner_window = ie >= 0 && je >= 0 && ie + EX <= D.nx && je + EY <= D.ny;
   double acc = 0.0;
-  for (int k = 0; k < K; ++k) {
-    const int cur = k & 1;
-#pragma unroll
-    for (int s = 0; s < PPT; ++s) {
-      const int lj = lw + s * RSTEP, r = lj + 1;
-      const T rr = heat::residual<T>(bb[s], tt[s], kl[s], sm.t[cur][r][c - 1], kr[s], sm.t[cur][r][c + 1], kd[s],
-                                     sm.t[cur][r - 1][c], ku[s], sm.t[cur][r + 1][c], dd[s]);
-      T un = tt[s], vn = vv[s];
-      heat::update<T>(ca, cc, dt, rr, un, vn);
-      tt[s] = cell[s] ? un : tt[s];
-      vv[s] = cell[s] ? vn : vv[s];
-      if (CHECK && k == K - 1) {
-        const bool inner = li >= K && li < EX - K && lj >= K && lj < EY - K && cell[s];
-        acc += inner ? (double)rr * (double)rr : 0.0;
-      }
-      sm.t[cur ^ 1][r][c] = tt[s];
-    }
-    __syncthreads();
-  }
+  if (inner_window) heat_tb_sweeps<T, K, CHECK, true>(sm, tt, vv, bb, kl, kr, kd, ku, dd, cell, li, lw, c, ca, cc, dt, acc);
+  else heat_tb_sweeps<T, K, CHECK, false>(sm, tt, vv, bb, kl, kr, kd, ku, dd, cell, li, lw, c, ca, cc, dt, acc);
 #pragma unroll
   for (int s = 0; s < PPT; ++s) {
     const int lj = lw + s * RSTEP, j = je + lj;

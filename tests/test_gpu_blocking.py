@@ -12,10 +12,13 @@ pytestmark = pytest.mark.gpu
 
 
 @pytest.mark.parametrize("prec,ks", [("fp32", (1, 2, 4, 5, 8, 10)), ("fp64", (1, 2, 4, 5))])
-@pytest.mark.parametrize("name", ["mixed2d", "cant2d_ragged"])
+@pytest.mark.parametrize("name", ["mixed2d", "cant2d_ragged", "cant2d_wide"])
 def test_blocking_bit_identical(name, prec, ks):
+    """Windows on the boundary and (ragged, wide) windows strictly inside the grid,
+    which take the kernel's ghost-free path."""
     require_gpu()
-    prob = mixed_elastic(2) if name == "mixed2d" else W.cantilever2d(203, 61)
+    prob = {"mixed2d": lambda: mixed_elastic(2), "cant2d_ragged": lambda: W.cantilever2d(203, 61),
+            "cant2d_wide": lambda: W.cantilever2d(300, 150)}[name]()
     announce(f"blocking {name} {prec} ks={ks}")
     phi = W.random_phi(prob, 6, 0.2, 1.0)
     u0 = W.random_u(prob, 7, scale=1e-2)

@@ -150,3 +150,64 @@ def test_full_size_residual_parity(name, make, sample):
         got, want = got.ravel()[flat], want.ravel()[flat]
     err = np.abs(got - want).max() / scale
     assert err < 2e-6, err
+
+
+def _fp32(a):
+    return np.asarray(a).astype(np.float32).astype(np.float64)
+
+
+@pytest.mark.parametrize("name,make", [
+    ("cantilever2d_1024x512", lambda: W.cantilever2d(1024, 512)),
+    ("cantilever3d_128x64x64", lambda: W.cantilever3d(128, 64, 64)),
+])
+def test_full_size_sweeps_parity(name, make):
+    """At full size and in the launch configuration the bench times (FP32 graphs,
+    autotuned sweeps per launch in 2D, the automatic 3D tiling): 20 sweeps from a
+    random state against the oracle's 20 FP64 sweeps, every unknown."""
+    require_gpu()
+    prob = make()
+    announce(f"full-size sweeps {name}")
+    phi = _fp32(W.random_phi(prob, 12, 0.05, 1.0))
+    u0 = _fp32(W.random_u(prob, 13, scale=1e-3))
+    ctx = context(prob, "fp32")
+    phi_t = dev(phi, torch.float32)
+    u = dev(u0, torch.float32)
+    v = ctx.new_state()
+    # a first solve runs the autotuner (2D), as in the bench
+    ctx.solve(phi_t, ctx.new_state(), ctx.new_state(), theta=1.0, replay_iters=20, check_every=20)
+    st, info = ctx.solve(phi_t, u, v, theta=1.0, replay_iters=20, check_every=20)
+    assert info[0]["iters"] == 20
+    got = host(u, prob.u_shape())
+    blocking, tiling = ctx.blocking(), (ctx.tile3d() if prob.ndim == 3 else None)
+    ctx.close()
+    res, _ = design.solve(phi, prob, u0=u0, params=design.AptParams(theta=1.0, check_every=20), n_iter=20)
+    err = rel_l2(got, res.u)
+    assert err < 2e-5, (blocking, tiling, err)
+    assert info[0]["rel_res"] == pytest.approx(res.rho, rel=1e-3)
+
+
+def test_full_size_heat_batch_sweeps_parity():
+    """The 64-design heat batch at full size (22.0 M cells), 20 FP32 sweeps in the
+    bench's launch configuration; four seeded designs compared with the oracle on
+    every cell, the rest checked for finiteness."""
+    require_gpu()
+    probs, phis, _ = W.heat_batch()
+    announce("full-size heat batch sweeps")
+    rng = np.random.default_rng(14)
+    u0 = [_fp32(rng.uniform(0.0, 1e-2, p.cell_shape())) for p in probs]
+    phis = [_fp32(x) for x in phis]
+    ctx = context(probs, "fp32")
+    phi_t = dev(np.concatenate([x.ravel() for x in phis]), torch.float32)
+    ctx.solve(phi_t, ctx.new_state(), ctx.new_state(), theta=1.0, replay_iters=20, check_every=20)
+    u = dev(np.concatenate([x.ravel() for x in u0]), torch.float32)
+    v = ctx.new_state()
+    st, info = ctx.solve(phi_t, u, v, theta=1.0, replay_iters=20, check_every=20)
+    got = host(u)
+    assert np.all(np.isfinite(got))
+    offs = [(ctx.offset(d, 1), ctx.offset(d + 1, 1)) for d in range(len(probs))]
+    ctx.close()
+    for d in sorted(rng.choice(len(probs), 4, replace=False)):
+        p = probs[d]
+        res, _ = design.solve(phis[d], p, u0=u0[d], params=design.AptParams(theta=1.0, check_every=20), n_iter=20)
+        o0, o1 = offs[d]
+        assert rel_l2(got[o0:o1].reshape(p.cell_shape()), res.u) < 2e-5, d
