@@ -17,10 +17,11 @@ namespace {
 
 constexpr int TX = 64;
 constexpr int LX = TX + 3;   // halo column on each side, plus the x = nx face column
+// (likewise LY = TY + 3 rows: halo rows and the y = ny face row)
 
 template <typename T, int TY>
 struct Sm3 {
-  static constexpr int LY = TY + 2;
+  static constexpr int LY = TY + 3;
   T u[2][3][LY][LX];        // state planes (parity of the layer), with halo
   T e[2][LY][LX];           // cell moduli of the same layers
   T sxx[LY][LX], syy[LY][LX];
@@ -54,11 +55,11 @@ __device__ __forceinline__ T face3(const ElGeom& g, const T* __restrict__ u, int
   return sgn * u[(long)a * g.plane + ((long)id[2] * g.py + id[1]) * g.px + id[0]];
 }
 
-// Staging of one z-layer: each thread fetches its share of the (TY+2) x (TX+2)
-// halo plane into registers (ahead of time) and later stores it to LDS.
+// Staging of one z-layer: each thread fetches its share of the (TY+3) x (TX+3)
+// plane into registers (ahead of time) and later stores it to LDS.
 template <typename T, int TY>
 struct Plane {
-  static constexpr int LY = TY + 2;
+  static constexpr int LY = TY + 3;
   static constexpr int NE = (LY * LX + TX * TY - 1) / (TX * TY);
   T v[NE][4];   // u_x, u_y, u_z, modulus
 };
@@ -66,7 +67,7 @@ struct Plane {
 template <typename T, int TY>
 __device__ __forceinline__ void fetch_plane(const ElGeom& g, const T* __restrict__ u, const T* __restrict__ E,
                                             int i0, int j0, int k, Plane<T, TY>& P) {
-  constexpr int LY = TY + 2;
+  constexpr int LY = TY + 3;
 #pragma unroll
   for (int e = 0; e < Plane<T, TY>::NE; ++e) {
     const int q = threadIdx.x + e * TX * TY;
@@ -91,7 +92,7 @@ __device__ __forceinline__ void fetch_plane(const ElGeom& g, const T* __restrict
 
 template <typename T, int TY>
 __device__ __forceinline__ void store_plane(const Plane<T, TY>& P, int buf, Sm3<T, TY>& sm) {
-  constexpr int LY = TY + 2;
+  constexpr int LY = TY + 3;
 #pragma unroll
   for (int e = 0; e < Plane<T, TY>::NE; ++e) {
     const int q = threadIdx.x + e * TX * TY;
@@ -115,7 +116,7 @@ __device__ __forceinline__ bool edge_ok(int idx, int n, int clo, int chi, bool& 
 template <typename T, int TY>
 __device__ __forceinline__ void xz_yz_planes(const ElGeom& g, int i0, int j0, int kz, int lo, int up, int dst,
                                              T rh, T mu0, Sm3<T, TY>& sm) {
-  constexpr int LY = TY + 2;
+  constexpr int LY = TY + 3;
   for (int q = threadIdx.x; q < LY * LX; q += TX * TY) {
     const int b = q / LX, a = q - b * LX;
     const int i = i0 - 1 + a, j = j0 - 1 + b;
@@ -185,17 +186,18 @@ __device__ __forceinline__ void zero_slot(const ElSweep<T>& A, long gi) {
   else A.b32[gi] = 0.f;
 }
 
-// Tiling: x-tiles of TX positions cover i < nx, and the tile ending at i = nx - 1
-// also takes the face column i = nx (only u_x lives there) through TY of its
-// threads; y-tiles of TY rows cover j <= ny; z-tiles of KZ layers, the last one
-// running through layer nz.
+// Tiling: x-tiles of TX positions cover i < nx, and a tile ending at i = nx - 1
+// also takes the face column i = nx (only u_x lives there) through TY + 1 threads
+// of its first wave; y-tiles of TY rows cover j < ny, and a tile ending at
+// j = ny - 1 also takes the face row j = ny (only u_y) through its last wave;
+// z-tiles of KZ layers, the last one running through layer nz.
 template <typename T, int TY, int KZ, int MODE>
 __global__ __launch_bounds__(TX * TY) void el3d_stream_kernel(ElGeom g, ElSweep<T> A, int tiles_x, int tiles_y,
                                                               int ntiles) {
   if (MODE == kSweep || MODE == kCheck || (MODE == kRefine && A.st != nullptr)) {
     if (A.st->done) return;
   }
-  constexpr int LY = TY + 2;
+  constexpr int LY = TY + 3;
   constexpr int XA = TX + 1;             // LDS column of the face column i = i0 + TX
   __shared__ Sm3<T, TY> sm;
   const int tile = xcd_tile(blockIdx.x, ntiles);
@@ -216,9 +218,15 @@ __global__ __launch_bounds__(TX * TY) void el3d_stream_kernel(ElGeom g, ElSweep<
     cc = T(A.st->c);
     dt = T(A.st->dt);
   }
-  // face-column duty: thread t < TY takes row t of the column i = nx
+  // face-row duty (j = ny): the last wave, lane l takes position i0 + l
+  const bool yrow = j0 + TY == ny && (int)threadIdx.x / TX == TY - 1;
+  const int fi = i0 + (int)(threadIdx.x % TX);
+  const bool yface = yrow && fi <= nx;
+  const bool yfok = yface && fi < nx;
+  // face-column duty (i = nx): thread t <= TY takes row j0 + t of the column
+  // (row TY only when this tile also holds the face row: the corner slot)
   const int ej = j0 + (int)threadIdx.x;
-  const bool xface = i0 + TX == nx && (int)threadIdx.x < TY && ej <= ny;
+  const bool xface = i0 + TX == nx && ej <= ny && ((int)threadIdx.x < TY || ((int)threadIdx.x == TY && j0 + TY == ny));
   const bool xfok = xface && ej < ny;
   const int kend = (tz == ntiles / txy - 1) ? nz + 1 : k0 + KZ;
   // prologue: planes k0-1 (into buffer 1) and k0 (buffer 0); xz/yz shear at z = k0
@@ -257,11 +265,19 @@ __global__ __launch_bounds__(TX * TY) void el3d_stream_kernel(ElGeom g, ElSweep<
       if (MODE == kSweep || MODE == kCheck) vxe = A.v[pe];
       bxe = A.b[pe];
     }
+    const long pf = ((long)k * g.py + ny) * g.px + fi;
+    const bool yok = yfok && k < nz;
+    T vye = T(0), bye = T(0);
+    if (yok) {
+      if (MODE == kSweep || MODE == kCheck) vye = A.v[pl + pf];
+      bye = A.b[pl + pf];
+    }
     __syncthreads();
     // fetch plane k+2 while this layer computes
     if (k + 1 < kend) fetch_plane<T, TY>(g, A.uin, A.E, i0, j0, k + 2, P);
     const T uo[3] = {sm.u[cur][0][b][a], sm.u[cur][1][b][a], sm.u[cur][2][b][a]};
     const T uxe = xok ? sm.u[cur][0][1 + threadIdx.x][XA] : T(0);
+    const T uye = yok ? sm.u[cur][1][TY + 1][1 + threadIdx.x % TX] : T(0);
     // normal stresses (cells of layer k) and xy shear (layer k)
     for (int q = threadIdx.x; q < LY * LX; q += TX * TY) {
       const int bb2 = q / LX, aa = q - bb2 * LX;
@@ -329,6 +345,20 @@ __global__ __launch_bounds__(TX * TY) void el3d_stream_kernel(ElGeom g, ElSweep<
       zero_slot<T, MODE>(A, pl + pe);
       zero_slot<T, MODE>(A, 2 * pl + pe);
     }
+    // the face row j = ny: u_y only (u_x, u_z slots are padding)
+    if (yface) {
+      const int fa = 1 + (int)(threadIdx.x % TX), fb = TY + 1;
+      if (yok) {
+        const T r = el3d::residual<T>(bye, h2, sm.syy[fb][fa], sm.syy[fb - 1][fa], sm.txy[fb][fa + 1],
+                                      sm.txy[fb][fa], sm.tyz[up][fb][fa], sm.tyz[cur][fb][fa]);
+        const bool fix = g.fixn[3] || pinned3s(g.pins, pl + pf);
+        finish<T, MODE>(A, pl + pf, fix, r, uye, vye, ca, cc, dt, acc);
+      } else {
+        zero_slot<T, MODE>(A, pl + pf);
+      }
+      zero_slot<T, MODE>(A, pf);
+      zero_slot<T, MODE>(A, 2 * pl + pf);
+    }
     szz_prev = szz_cur;
     cur = up;
     // the next store writes the plane read before the barrier above, and the
@@ -352,7 +382,7 @@ template <> struct Cfg3<double, 2> { static constexpr int TY = 4, KZ = 4; };
 template <typename T, int V>
 void tiles_s(const ElGeom& g, int& tx, int& ty, int& tz) {
   tx = (g.nx + TX - 1) / TX;
-  ty = (g.ny + 1 + Cfg3<T, V>::TY - 1) / Cfg3<T, V>::TY;
+  ty = (g.ny + Cfg3<T, V>::TY - 1) / Cfg3<T, V>::TY;
   tz = (g.nz + Cfg3<T, V>::KZ - 1) / Cfg3<T, V>::KZ;
 }
 
