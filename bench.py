@@ -48,7 +48,8 @@ def parse():
     ap.add_argument("--no-timing", action="store_true", help="skip the library's sweep-block events")
     ap.add_argument("--workload", default="cantilever2d",
                     help="cantilever2d (design steps, the default line) or, for sweep throughput only: "
-                         "heat_batch64, cantilever3d_128x64x64, multimaterial3d_256x128x128")
+                         "heat_batch64, cantilever3d_NXxNYxNZ, multimaterial3d_NXxNYxNZ (e.g. 256x128x128, "
+                         "or 256x128x18 for one GPU's z-slab of an 8-way split with its halo layers)")
     ap.add_argument("--sweeps", type=int, default=2000, help="sweep-throughput legs: sweeps to time")
     ap.add_argument("--adapt", action="store_true",
                     help="re-choose the damping at every check from the state's Rayleigh quotient")
@@ -64,25 +65,33 @@ def cpu_baseline(prob, phi0, sweeps):
     import numpy as np
     from oracle import design
 
+    c0 = time.process_time()
     t0 = time.perf_counter()
     res, _ = design.solve(phi0, prob, params=design.AptParams(theta=1.0, check_every=100), n_iter=sweeps)
     t1 = time.perf_counter()
     g = design.sensitivity(res.u, phi0, prob)
     design.phase_update(phi0, g, prob)
     dt = time.perf_counter() - t0
+    busy = (time.process_time() - c0) / dt      # CPU seconds per wall second
     cores = len(os.sched_getaffinity(0))
     value = prob.ncell * sweeps / dt
-    return {"value": value, "unit": "cell-updates/s", "cores": 1, "cores_available": cores, "kind": "oracle",
+    return {"value": value, "unit": "cell-updates/s", "cores": max(1, round(busy)), "cpu_busy": round(busy, 2),
+            "cores_available": cores, "kind": "oracle",
             "seconds": round(dt, 3), "sweep_seconds": (t1 - t0) / sweeps,
             "sensitivity_and_phase_seconds": dt - (t1 - t0),
             "sample": f"{sweeps} sweeps from rest + 1 sensitivity + 1 phase update on the full "
-                      f"{prob.n[0]}x{prob.n[1]} grid (FP64 NumPy/SciPy, single-threaded sparse products)"}
+                      f"{prob.n[0]}x{prob.n[1]} grid (FP64 NumPy/SciPy; cores = CPU seconds per wall second, rounded)"}
 
 
 # Algorithmic bytes per cell and sweep of the other FP32 sweep kernels: state and
 # velocity read + written, material read, and (3D) the load read; the heat batch
 # has a uniform source.
-BYTES_PER_CELL = {"heat_batch64": 20, "cantilever3d_128x64x64": 64, "multimaterial3d_256x128x128": 64}
+def bytes_per_cell(workload):
+    if workload.startswith("heat"):
+        return 20
+    if "3d_" in workload:
+        return 64
+    return BYTES_PER_CELL_2D_FP32
 
 
 # Sources whose text decides each kernel family's memory traffic: a recorded
@@ -164,7 +173,7 @@ def sweep_leg(args):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms, n = ctx.last_sweep_ms()
-    bpc = BYTES_PER_CELL[args.workload]
+    bpc = bytes_per_cell(args.workload)
     family = "heat" if args.workload.startswith("heat") else ("el3d" if "3d" in args.workload else "el2d")
     roof = kernel_roofline(ctx, bpc * ncell, family, args.workload)
     roof["bytes_per_cell"] = bpc

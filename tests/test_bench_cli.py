@@ -1,0 +1,40 @@
+"""Host-side checks of the benchmark driver (no GPU)."""
+import json
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert p.returncode == 2
+    assert "one GPU" in json.loads(p.stdout.strip().splitlines()[-1])["error"]
+
+
+def test_bytes_per_cell():
+    assert bench.bytes_per_cell("heat_batch64") == 20
+    assert bench.bytes_per_cell("multimaterial3d_256x128x18") == 64
+    assert bench.bytes_per_cell("cantilever2d_1024x512") == 44
+
+
+def test_recorded_traffic_needs_matching_sources(tmp_path, monkeypatch):
+    digest = bench.source_digest("el2d")
+    rec = {"k @ w": {"source_digest": digest, "fetch_kib": 10.0, "fetch_factor": 2.0, "write_kib": 4.0,
+                     "write_factor": 1.0}}
+    (tmp_path / "profiles").mkdir()
+    (tmp_path / "profiles" / "traffic.json").write_text(json.dumps(rec))
+    real_root = bench.ROOT
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    # sources are read from the real tree
+    monkeypatch.setattr(bench, "source_digest", lambda fam: digest)
+    assert bench.recorded_traffic("el2d", "k", "w") == (10.0 * 2.0 + 4.0) * 1024
+    monkeypatch.setattr(bench, "source_digest", lambda fam: "changed")
+    assert bench.recorded_traffic("el2d", "k", "w") is None
+    assert bench.recorded_traffic("el2d", "other", "w") is None
+    assert real_root
