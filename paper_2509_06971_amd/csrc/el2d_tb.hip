@@ -112,8 +112,11 @@ __device__ __forceinline__ void tb_sweeps(const ElGeom& g, TbSmem<T>& sm, T (&ux
 // region anyway).
 template <typename T, int K, bool CHECK>
 __global__ __launch_bounds__(NT) void el2d_tb_kernel(ElGeom g, ElSweep<T> A, int tiles_x, int ntiles) {
-  if (A.st->done) return;
   static_assert(EX - 2 * K > 0 && EY - 2 * K > 0, "window too small for K sweeps");
+  // the stop flag and coefficients are read up front, so their latency overlaps
+  // the window loads; the early exit comes after the loads are issued
+  const int done = A.st->done;
+  const T ca = T(A.st->a), cc = T(A.st->c), dt = T(A.st->dt);
   constexpr int TXI = EX - 2 * K, TYI = EY - 2 * K;
   __shared__ TbSmem<T> sm;
   const int tile = xcd_tile(blockIdx.x, ntiles);
@@ -167,6 +170,7 @@ __global__ __launch_bounds__(NT) void el2d_tb_kernel(ElGeom g, ElSweep<T> A, int
     sm.dx[lj + 1][c] = ux[s];
     sm.dy[lj + 1][c] = uy[s];
   }
+  if (done) return;   // uniform over the workgroup, before its first barrier
   __syncthreads();
   const T lam0 = T(g.lam0), mu0 = T(g.mu0);
 #pragma unroll
@@ -185,7 +189,6 @@ __global__ __launch_bounds__(NT) void el2d_tb_kernel(ElGeom g, ElSweep<T> A, int
   __syncthreads();
 
   const T rh = T(1.0 / g.h), h = T(g.h);
-  const T ca = T(A.st->a), cc = T(A.st->c), dt = T(A.st->dt);
   // A window that lies strictly inside the grid and holds no pinned unknown has
   // no ghosts and no fixed unknowns: its sweeps skip those selects.
   const bool inner_window = ie >= 1 && je >= 1 && ie + EX <= nx && je + EY <= ny && g.pins == nullptr;

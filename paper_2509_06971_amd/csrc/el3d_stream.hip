@@ -194,9 +194,10 @@ __device__ __forceinline__ void zero_slot(const ElSweep<T>& A, long gi) {
 template <typename T, int TY, int KZ, int MODE>
 __global__ __launch_bounds__(TX * TY) void el3d_stream_kernel(ElGeom g, ElSweep<T> A, int tiles_x, int tiles_y,
                                                               int ntiles) {
-  if (MODE == kSweep || MODE == kCheck || (MODE == kRefine && A.st != nullptr)) {
-    if (A.st->done) return;
-  }
+  // the stop flag is read up front and tested after the first planes' loads are
+  // issued, so the latencies overlap
+  int done = 0;
+  if (MODE == kSweep || MODE == kCheck || (MODE == kRefine && A.st != nullptr)) done = A.st->done;
   constexpr int LY = TY + 3;
   constexpr int XA = TX + 1;             // LDS column of the face column i = i0 + TX
   __shared__ Sm3<T, TY> sm;
@@ -236,6 +237,7 @@ __global__ __launch_bounds__(TX * TY) void el3d_stream_kernel(ElGeom g, ElSweep<
   store_plane<T, TY>(P, 1, sm);
   fetch_plane<T, TY>(g, A.uin, A.E, i0, j0, k0, P);
   store_plane<T, TY>(P, 0, sm);
+  if (done) return;   // uniform over the workgroup, before its first barrier
   __syncthreads();
   fetch_plane<T, TY>(g, A.uin, A.E, i0, j0, k0 + 1, P);
   xz_yz_planes<T, TY>(g, i0, j0, k0, 1, 0, 0, rh, mu0, sm);

@@ -63,11 +63,14 @@ __device__ __forceinline__ void heat_tb_sweeps(HTb<T>& sm, T (&tt)[PPT], T (&vv)
 
 template <typename T, int K, bool CHECK>
 __global__ __launch_bounds__(NT) void heat2d_tb_kernel(HeatSweep<T> A) {
-  if (*A.all_done) return;
+  // stop flags and coefficients are read up front, and the early exit comes after
+  // the window loads are issued, so their latencies overlap
+  const int all_done = *A.all_done;
   const int tile = xcd_tile(blockIdx.x, A.ntile);
   const HeatTile tl = A.tiles[tile];
   const SolveState* st = &A.st[tl.design];
-  if (st->done) return;
+  const int done = st->done;
+  const T ca = T(st->a), cc = T(st->c), dt = T(st->dt);
   const HeatDesign D = A.des[tl.design];
   __shared__ HTb<T> sm;
   const int ie = tl.i0 - K, je = tl.j0 - K;
@@ -103,6 +106,7 @@ __global__ __launch_bounds__(NT) void heat2d_tb_kernel(HeatSweep<T> A) {
     sm.t[0][lj + 1][c] = tt[s];
     sm.k[lj + 1][c] = kc[s];
   }
+  if (all_done || done) return;   // uniform over the workgroup, before its first barrier
   __syncthreads();
   T kl[PPT], kr[PPT], kd[PPT], ku[PPT];
 #pragma unroll
@@ -113,7 +117,6 @@ __global__ __launch_bounds__(NT) void heat2d_tb_kernel(HeatSweep<T> A) {
     kd[s] = heat::face<T>(kc[s], sm.k[r - 1][c], j > 0);
     ku[s] = heat::face<T>(kc[s], sm.k[r + 1][c], j < D.ny - 1);
   }
-  const T ca = T(st->a), cc = T(st->c), dt = T(st->dt);
   // a window inside its design: every position is a cell (no selects)
   const bool inner_window = ie >= 0 && je >= 0 && ie + EX <= D.nx && je + EY <= D.ny;
   double acc = 0.0;
