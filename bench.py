@@ -43,7 +43,7 @@ def parse():
     ap.add_argument("--ny", type=int, default=512)
     ap.add_argument("--theta", type=float, default=1.0)
     ap.add_argument("--tol", type=float, default=1e-6)
-    ap.add_argument("--cpu-sweeps", type=int, default=1000)
+    ap.add_argument("--cpu-sweeps", type=int, default=2000)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-timing", action="store_true", help="skip the library's sweep-block events")
     ap.add_argument("--workload", default="cantilever2d",
