@@ -21,7 +21,7 @@ def _elastic_cases():
 
 
 def _tilings(prob):
-    """3D contexts: both sweep tilings; 2D: the default."""
+    """3D contexts: every sweep tiling; 2D: the default."""
     return [1, 2] if prob.ndim == 3 else [None]
 
 
