@@ -214,26 +214,37 @@ def residual(u, E, prob, F=None):
 def modulus(phi, prob):
     """Young's modulus per cell.  Single phase: the modified SIMP law
     E = Emin + phi^p (E0 - Emin).  Several solid phases plus void: the sum of
-    E_m phi_m^p over the solid phases and the void phase 1 - sum(phi) (Eq. (3.8))."""
+    E_m phi_m^p over the solid phases and the void phase 1 - sum(phi) (Eq. (3.8)).
+    The laws take every phase fraction clamped to [0, 1] (a reading: fractions can
+    leave the range under the penalty update of Eq. (2.13))."""
+    q = np.clip(phi, 0.0, 1.0)
     if prob.nphase > 1:
-        void = 1.0 - phi.sum(axis=0)
+        void = np.clip(1.0 - q.sum(axis=0), 0.0, 1.0)
         E = prob.e_phase[-1] * void ** prob.p
         for m in range(prob.nphase):
-            E = E + prob.e_phase[m] * phi[m] ** prob.p
+            E = E + prob.e_phase[m] * q[m] ** prob.p
         return E
-    return prob.emin + phi[0] ** prob.p * (prob.e0 - prob.emin)
+    return prob.emin + q[0] ** prob.p * (prob.e0 - prob.emin)
+
+
+def _inside(x):
+    return ((x >= 0.0) & (x <= 1.0)).astype(np.float64)
 
 
 def modulus_derivative(phi, prob):
-    """dE/dphi_m per stored phase (shape of phi)."""
+    """dE/dphi_m per stored phase (shape of phi); zero where a clamped fraction
+    is outside [0, 1]."""
     p = prob.p
+    q = np.clip(phi, 0.0, 1.0)
     if prob.nphase > 1:
-        void = 1.0 - phi.sum(axis=0)
+        vraw = 1.0 - q.sum(axis=0)
+        void = np.clip(vraw, 0.0, 1.0)
         out = np.empty_like(phi)
         for m in range(prob.nphase):
-            out[m] = p * (prob.e_phase[m] * phi[m] ** (p - 1) - prob.e_phase[-1] * void ** (p - 1))
+            out[m] = p * (prob.e_phase[m] * q[m] ** (p - 1) * _inside(phi[m])
+                          - prob.e_phase[-1] * void ** (p - 1) * _inside(vraw))
         return out
-    return (p * phi[0] ** (p - 1) * (prob.e0 - prob.emin))[None]
+    return (p * q[0] ** (p - 1) * (prob.e0 - prob.emin) * _inside(phi[0]))[None]
 
 
 def p_wave_max(E, prob):

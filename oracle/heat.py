@@ -17,12 +17,17 @@ import numpy as np
 
 
 def conductivity(phi, prob):
-    """k = kmin + phi^p (k0 - kmin): the modified SIMP form of Eq. (3.1)."""
-    return prob.emin + phi[0] ** prob.p * (prob.e0 - prob.emin)
+    """k = kmin + phi^p (k0 - kmin): the modified SIMP form of Eq. (3.1), on phi
+    clamped to [0, 1] (as the elastic laws)."""
+    q = np.clip(phi[0], 0.0, 1.0)
+    return prob.emin + q ** prob.p * (prob.e0 - prob.emin)
 
 
 def conductivity_derivative(phi, prob):
-    return (prob.p * phi[0] ** (prob.p - 1) * (prob.e0 - prob.emin))[None]
+    """dk/dphi; zero where phi is outside [0, 1]."""
+    q = np.clip(phi[0], 0.0, 1.0)
+    inside = ((phi[0] >= 0.0) & (phi[0] <= 1.0)).astype(np.float64)
+    return (prob.p * q ** (prob.p - 1) * (prob.e0 - prob.emin) * inside)[None]
 
 
 def _ax(ndim, a):
