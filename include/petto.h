@@ -118,21 +118,41 @@ typedef struct {
   int32_t use_graph;
   int32_t replay_iters;
   int32_t adapt;
+  int32_t n_pt;             /* > 0: after the damped-wave sweeps, n_pt plain PT sweeps
+                               (theta = 0, even count, no stop rule): the paper's
+                               hybrid schedule (Section 3, n_APT + n_PT per loop) */
+  double dt_pt;             /* PT step of that stage; <= 0: h^2 / (2 d M_max) */
 } petto_apt_params;
 
-/* Design update controls (Sections 2.4, 3.1).  phi' = phi - alpha_h g / max|g|
+enum { PETTO_UPDATE_ALLEN_CAHN = 0, PETTO_UPDATE_PENALTY_CH = 1 };
+
+/* Design update controls (Sections 2.4, 3.1).
+ * model PETTO_UPDATE_ALLEN_CAHN:   phi' = phi - alpha_h g / max|g|
  * (Eq. 3.2 step), phi'' = phi' - dt_ac (w'(phi') - gamma lap phi') with
  * w = sin^2(pi phi)/64 (Eq. 2.15) and mirror boundaries, then
  * phi = clamp(phi'' + s, 0, ub) with s such that mean(phi) = vol_frac (ub = 1 for
  * the first phase, 1 - phi1 for the second).  dt_ac <= 0 selects
  * 0.9 min(h^2 / (4 d gamma), 32 / pi^2).  bisect_passes <= 0 selects the default
- * (9 passes of a 64-way bracket split, bracket width <= 2^-54 of the start). */
+ * (9 passes of a 64-way bracket split, bracket width <= 2^-54 of the start).
+ * model PETTO_UPDATE_PENALTY_CH (the paper's own update, Eq. 2.13 with the
+ * normalised sensitivity of Section 3.1, then one explicit step of Eq. 2.14):
+ *   phi' = phi - alpha_h g / max|g| - alpha_v dJ_v/dphi - alpha_1 dJ_1/dphi,
+ *   dJ_v/dphi = 2 (h^d sum phi - vol_frac N h^d) h^d,  dJ_1/dphi = 2 (sum_m phi_m - 1) h^d,
+ *   phi = phi' + dt_ch D lap(w'(phi') - gamma lap phi'), mirror boundaries,
+ * every phase from the same old design; no clamp and no projection (the material
+ * laws evaluate fractions clamped to [0, 1]).  info.shift receives the uniform
+ * volume-penalty term -alpha_v dJ_v/dphi. */
 typedef struct {
   double alpha_h;
   double gamma;
   double dt_ac;
   double vol_frac[2];
   int32_t bisect_passes;
+  int32_t model;            /* PETTO_UPDATE_ALLEN_CAHN (above) or PETTO_UPDATE_PENALTY_CH */
+  double alpha_v;           /* penalty model: volume-penalty weight (paper: 1e5) */
+  double alpha_1;           /* penalty model: partition-of-unity weight (0 with an implicit void) */
+  double dt_ch;             /* penalty model: Cahn-Hilliard step; <= 0: 500 h^4 */
+  double mobility;          /* penalty model: D of Eq. 2.14; <= 0: 1 */
 } petto_phase_params;
 
 typedef struct {
@@ -147,7 +167,7 @@ typedef struct {
 } petto_solve_info;
 
 typedef struct {
-  double shift[2];          /* volume multiplier s per phase */
+  double shift[2];          /* volume multiplier s per phase (penalty model: -alpha_v dJ_v/dphi) */
   double volume[2];         /* mean(phi) per phase after the update */
   double gmax[2];           /* max |g| per phase used for normalisation */
 } petto_phase_info;

@@ -33,14 +33,15 @@ class AptParams(C.Structure):
     _fields_ = [
         ("theta", C.c_double), ("dt", C.c_double), ("tol", C.c_double), ("max_iter", C.c_int32),
         ("check_every", C.c_int32), ("refine", C.c_int32), ("use_graph", C.c_int32),
-        ("replay_iters", C.c_int32), ("adapt", C.c_int32),
+        ("replay_iters", C.c_int32), ("adapt", C.c_int32), ("n_pt", C.c_int32), ("dt_pt", C.c_double),
     ]
 
 
 class PhaseParams(C.Structure):
     _fields_ = [
         ("alpha_h", C.c_double), ("gamma", C.c_double), ("dt_ac", C.c_double),
-        ("vol_frac", C.c_double * 2), ("bisect_passes", C.c_int32),
+        ("vol_frac", C.c_double * 2), ("bisect_passes", C.c_int32), ("model", C.c_int32),
+        ("alpha_v", C.c_double), ("alpha_1", C.c_double), ("dt_ch", C.c_double), ("mobility", C.c_double),
     ]
 
 

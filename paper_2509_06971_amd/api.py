@@ -92,22 +92,28 @@ class Context:
 
     @staticmethod
     def apt_params(theta=1.0, dt=0.0, tol=1e-6, max_iter=10**8, check_every=100, refine=False,
-                   use_graph=True, replay_iters=0, adapt=False):
+                   use_graph=True, replay_iters=0, adapt=False, n_pt=0, dt_pt=0.0):
         p = L.AptParams()
         p.theta, p.dt, p.tol = float(theta), float(dt), float(tol)
         p.max_iter, p.check_every = int(max_iter), int(check_every)
         p.refine, p.use_graph = int(bool(refine)), int(bool(use_graph))
         p.replay_iters = int(replay_iters)
         p.adapt = int(bool(adapt))
+        p.n_pt, p.dt_pt = int(n_pt), float(dt_pt)
         return p
 
     @staticmethod
-    def phase_params(vol_frac, alpha_h=0.1, gamma=3e-5, dt_ac=0.0, bisect_passes=0):
+    def phase_params(vol_frac, alpha_h=0.1, gamma=3e-5, dt_ac=0.0, bisect_passes=0, model="allen_cahn",
+                     alpha_v=1e5, alpha_1=0.0, dt_ch=0.0, mobility=1.0):
+        """model: "allen_cahn" (Allen-Cahn step + exact volume projection) or
+        "penalty" (the paper's penalty update + one Cahn-Hilliard step)."""
         p = L.PhaseParams()
         p.alpha_h, p.gamma, p.dt_ac = float(alpha_h), float(gamma), float(dt_ac)
         vf = list(vol_frac) + [0.0, 0.0]
         p.vol_frac[0], p.vol_frac[1] = float(vf[0]), float(vf[1])
         p.bisect_passes = int(bisect_passes)
+        p.model = {"allen_cahn": 0, "penalty": 1}[model]
+        p.alpha_v, p.alpha_1, p.dt_ch, p.mobility = float(alpha_v), float(alpha_1), float(dt_ch), float(mobility)
         return p
 
     # ------------------------------------------------------------------ entry points

@@ -206,12 +206,22 @@ struct PhaseArgs {
   long n;
   double h, alpha, gamma, dt_ac, target;
   int nblocks;
+  // the penalty / Cahn-Hilliard update
+  const T* other;           // the other stored phase (partition sum), or nullptr
+  double* work2;            // chemical potential mu (double)
+  double alpha_v, alpha_1, vol_frac, dt_ch, mobility;
 };
 template <typename T> void launch_phase_gmax(const PhaseArgs<T>& a, hipStream_t s);
 template <typename T> void launch_phase_step(const PhaseArgs<T>& a, hipStream_t s);
 template <typename T> void launch_phase_pass(const PhaseArgs<T>& a, hipStream_t s);
 template <typename T> void launch_phase_apply(const PhaseArgs<T>& a, hipStream_t s);
 int phase_blocks(long n);
+// The penalty update: max|g| and sum(phi) of the phase (into scal[0], scal[6]),
+// then phi' into work; then mu = w'(phi') - gamma lap(phi') into work2 and
+// phi = phi' + dt_ch D lap(mu), with the new mean into scal[4].
+template <typename T> void launch_penalty_prep(const PhaseArgs<T>& a, hipStream_t s);
+template <typename T> void launch_penalty_step(const PhaseArgs<T>& a, hipStream_t s);
+template <typename T> void launch_cahn_hilliard(const PhaseArgs<T>& a, hipStream_t s);
 
 // out[2d] = sum of pfu over design d's tiles, out[2d+1] = the same for pen.
 void launch_dot_finalize(const double* pfu, const double* pen, const int* tile0, int ntile, int ndes,

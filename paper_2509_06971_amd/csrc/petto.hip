@@ -110,6 +110,7 @@ struct petto_ctx {
   double* phase_scal = nullptr;
   double* phase_work = nullptr;
   double* phase_partial = nullptr;
+  double* pen_work = nullptr;          // penalty update: phi' per phase and mu ((nphase + 1) x cells)
   double* comp = nullptr;
   hipStream_t cap_stream = nullptr;
   hipEvent_t ev_end[kRing] = {};
@@ -383,6 +384,8 @@ petto_status check_apt_params(const petto_ctx* c, const petto_apt_params* p) {
     if (c->prec != PETTO_FP32) return fail(PETTO_ERR_INVALID, "refine applies to FP32 contexts only");
     if (p->replay_iters) return fail(PETTO_ERR_INVALID, "replay_iters cannot be combined with refine");
   }
+  if (p->n_pt < 0 || (p->n_pt & 1)) return fail(PETTO_ERR_INVALID, "n_pt must be even and >= 0");
+  if (!is_finite(p->dt_pt)) return fail(PETTO_ERR_INVALID, "dt_pt must be finite (<= 0 selects the default)");
   return PETTO_OK;
 }
 
@@ -830,6 +833,45 @@ petto_status phase_update_impl(petto_ctx* c, void* phi, const void* grad, const 
   T* ph = static_cast<T*>(phi);
   const T* g = static_cast<const T*>(grad);
   const int passes = pp->bisect_passes > 0 ? pp->bisect_passes : 9;
+  if (pp->model == PETTO_UPDATE_PENALTY_CH) {
+    if (c->pen_work == nullptr) PETTO_TRY(dalloc_t(c, &c->pen_work, (size_t)(c->nphase + 1) * c->max_cells));
+    for (int d = 0; d < c->nprob; ++d) {
+      const CellRange& R = c->h_ranges[d];
+      const double h = R.h;
+      std::vector<PhaseArgs<T>> args(c->nphase);
+      for (int m = 0; m < c->nphase; ++m) {
+        PhaseArgs<T>& a = args[m];
+        a.phi = ph + (long)m * c->ncell + R.off;
+        a.g = g + (long)m * c->ncell + R.off;
+        a.other = c->nphase == 2 ? ph + (long)(1 - m) * c->ncell + R.off : nullptr;
+        a.work = c->pen_work + (long)m * c->max_cells;
+        a.work2 = c->pen_work + (long)c->nphase * c->max_cells;
+        a.partial = c->phase_partial;
+        a.scal = c->phase_scal + (long)(2 * d + m) * 8;
+        a.nx = R.nx;
+        a.ny = R.ny;
+        a.nz = R.nz;
+        a.ndim = c->ndim;
+        a.n = R.n;
+        a.h = h;
+        a.alpha = pp->alpha_h;
+        a.gamma = pp->gamma;
+        a.alpha_v = pp->alpha_v;
+        a.alpha_1 = pp->alpha_1;
+        a.vol_frac = pp->vol_frac[m];
+        a.dt_ch = pp->dt_ch > 0.0 ? pp->dt_ch : 500.0 * h * h * h * h;
+        a.mobility = pp->mobility > 0.0 ? pp->mobility : 1.0;
+        a.nblocks = phase_blocks(R.n);
+      }
+      // every phase's step from the old design, then the Cahn-Hilliard steps
+      for (int m = 0; m < c->nphase; ++m) {
+        launch_penalty_prep<T>(args[m], s);
+        launch_penalty_step<T>(args[m], s);
+      }
+      for (int m = 0; m < c->nphase; ++m) launch_cahn_hilliard<T>(args[m], s);
+      HIP_TRY(hipGetLastError());
+    }
+  } else {
   for (int d = 0; d < c->nprob; ++d) {
     const CellRange& R = c->h_ranges[d];
     const double h = R.h;
@@ -864,6 +906,7 @@ petto_status phase_update_impl(petto_ctx* c, void* phi, const void* grad, const 
       launch_phase_apply<T>(a, s);
       HIP_TRY(hipGetLastError());
     }
+  }
   }
   if (info) {
     std::vector<double> sc((size_t)c->nprob * 16);
@@ -1248,9 +1291,41 @@ petto_status petto_apt_solve(petto_ctx* ctx, const void* phi, void* u, void* v, 
     ctx->timed_ms = 0.0;
     ctx->timed_sweeps = 0;
   }
-  if (params->refine) return solve_refine(ctx, phi, u, v, params, s, info);
-  if (ctx->prec == PETTO_FP64) return solve_plain<double>(ctx, phi, u, v, params, s, info);
-  return solve_plain<float>(ctx, phi, u, v, params, s, info);
+  auto stage = [&](const petto_apt_params* p, petto_solve_info* inf) -> petto_status {
+    if (p->refine) return solve_refine(ctx, phi, u, v, p, s, inf);
+    if (ctx->prec == PETTO_FP64) return solve_plain<double>(ctx, phi, u, v, p, s, inf);
+    return solve_plain<float>(ctx, phi, u, v, p, s, inf);
+  };
+  const petto_status s1 = stage(params, info);
+  if (s1 < 0 || params->n_pt == 0) return s1;
+  // the hybrid schedule's second stage: n_pt plain PT sweeps (theta = 0: the
+  // velocity plays no part), a fixed count without the stop rule
+  petto_apt_params q = *params;
+  q.theta = 0.0;
+  q.dt = params->dt_pt;
+  q.adapt = 0;
+  q.n_pt = 0;
+  q.check_every = (params->n_pt % params->check_every == 0) ? params->check_every : params->n_pt;
+  if (params->refine) {
+    q.tol = 0.0;                      // never met: the stage ends at max_iter
+    q.max_iter = params->n_pt;
+    q.replay_iters = 0;
+  } else {
+    q.replay_iters = params->n_pt;
+    q.max_iter = params->n_pt;
+  }
+  std::vector<petto_solve_info> pt(ctx->nprob);
+  const petto_status s2 = stage(&q, pt.data());
+  if (s2 < 0) return s2;
+  if (info) {
+    for (int d = 0; d < ctx->nprob; ++d) {
+      info[d].iters += pt[d].iters;
+      info[d].outer += pt[d].outer;
+      info[d].rel_res = pt[d].rel_res;
+      info[d].r_pde = pt[d].r_pde;
+    }
+  }
+  return s1;
 }
 
 petto_status petto_residual(petto_ctx* ctx, const void* phi, const void* u, void* r, void* stream) {
@@ -1314,6 +1389,14 @@ petto_status petto_phase_update(petto_ctx* ctx, void* phi, const void* grad_phi,
   if (!(pp->alpha_h >= 0.0) || !is_finite(pp->alpha_h)) return fail(PETTO_ERR_INVALID, "alpha_h must be >= 0");
   if (!(pp->gamma >= 0.0) || !is_finite(pp->gamma)) return fail(PETTO_ERR_INVALID, "gamma must be >= 0");
   if (!is_finite(pp->dt_ac)) return fail(PETTO_ERR_INVALID, "dt_ac must be finite");
+  if (pp->model != PETTO_UPDATE_ALLEN_CAHN && pp->model != PETTO_UPDATE_PENALTY_CH)
+    return fail(PETTO_ERR_INVALID, "unknown update model %d", pp->model);
+  if (pp->model == PETTO_UPDATE_PENALTY_CH) {
+    if (!(pp->alpha_v >= 0.0) || !is_finite(pp->alpha_v) || !(pp->alpha_1 >= 0.0) || !is_finite(pp->alpha_1))
+      return fail(PETTO_ERR_INVALID, "alpha_v and alpha_1 must be finite and >= 0");
+    if (!is_finite(pp->dt_ch) || !is_finite(pp->mobility))
+      return fail(PETTO_ERR_INVALID, "dt_ch and mobility must be finite (<= 0 selects the default)");
+  }
   double vs = 0.0;
   for (int m = 0; m < ctx->nphase; ++m) {
     if (!(pp->vol_frac[m] > 0.0 && pp->vol_frac[m] < 1.0))

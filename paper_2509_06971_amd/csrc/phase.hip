@@ -1,11 +1,15 @@
-// Phase-field design update (Sections 2.4 and 3.1): normalised sensitivity step
-// (Eq. 3.2 weight alpha_h), one explicit Allen-Cahn step with the double-well
-// w = sin^2(pi phi)/64 of Eq. 2.15 and mirror (no-flux) boundaries, and the volume
-// constraint enforced exactly by a uniform shift s: mean(clamp(phi'' + s, 0, ub)) = V.
+// Phase-field design update (Sections 2.4 and 3.1).
 //
-// The shift is found by a bracketed 64-way search: each pass evaluates the clamped
-// volume at 63 interior candidates of the current bracket in one sweep over the
-// cells (FP64 sums in a fixed order) and keeps the sub-interval holding the root.
+// Default model: normalised sensitivity step (Eq. 3.2 weight alpha_h), one
+// explicit Allen-Cahn step with the double-well w = sin^2(pi phi)/64 of Eq. 2.15
+// and mirror (no-flux) boundaries, and the volume constraint enforced exactly by a
+// uniform shift s: mean(clamp(phi'' + s, 0, ub)) = V.  The shift is found by a
+// bracketed 64-way search: each pass evaluates the clamped volume at 63 interior
+// candidates of the current bracket in one sweep over the cells (FP64 sums in a
+// fixed order) and keeps the sub-interval holding the root.
+//
+// The paper's own model: the penalty step of Eq. 2.13 and one explicit
+// Cahn-Hilliard step of Eq. 2.14 (two mirror-Laplacian passes).
 #include "kernels.hpp"
 
 namespace petto {
@@ -172,6 +176,101 @@ __global__ void volume_final_kernel(const double* partial, int nb, double* scal,
   if (threadIdx.x == 0) scal[4] = s / n;
 }
 
+// ---- the paper's own update: penalty step (Eq. 2.13, normalised sensitivity of
+// Section 3.1) and one explicit Cahn-Hilliard step (Eq. 2.14)
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void sum_kernel(PhaseArgs<T> A) {
+  __shared__ double red[kBlock / kWave];
+  double acc = 0.0;
+  for (long c = (long)blockIdx.x * kBlock + threadIdx.x; c < A.n; c += (long)gridDim.x * kBlock)
+    acc += (double)A.phi[c];
+  const double t = block_sum(acc, red);
+  if (threadIdx.x == 0) A.partial[blockIdx.x] = t;
+}
+
+__global__ void sum_final_kernel(const double* partial, int nb, double* scal) {
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nb; b += kWave) s += partial[b];
+  s = wave_sum(s);
+  if (threadIdx.x == 0) scal[6] = s;
+}
+
+// phi' = phi - alpha_h g / max|g| - alpha_v dJ_v/dphi - alpha_1 dJ_1/dphi (every
+// phase from the old design), with dJ_v/dphi = 2 (h^d sum phi - V N h^d) h^d and
+// dJ_1/dphi = 2 (sum_m phi_m - 1) h^d.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void penalty_kernel(PhaseArgs<T> A) {
+  const double gmax = A.scal[0];
+  const double hd = A.ndim == 3 ? A.h * A.h * A.h : A.h * A.h;
+  const double vpen = A.alpha_v * (2.0 * (hd * A.scal[6] - A.vol_frac * (double)A.n * hd) * hd);
+  for (long c = (long)blockIdx.x * kBlock + threadIdx.x; c < A.n; c += (long)gridDim.x * kBlock) {
+    const double f = (double)A.phi[c];
+    const double gh = gmax > 0.0 ? (double)A.g[c] / gmax : 0.0;
+    double y = (f - A.alpha * gh) - vpen;
+    if (A.alpha_1 != 0.0) {
+      const double tot = A.other != nullptr ? f + (double)A.other[c] : f;
+      y = y - A.alpha_1 * (2.0 * (tot - 1.0) * hd);
+    }
+    A.work[c] = y;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) A.scal[3] = -vpen;
+}
+
+// Mirror-boundary Laplacian of a double field at cell (i, j, k).
+__device__ inline double lap_mirror(const double* x, long c, int i, int j, int k, int nx, int ny, int nz, int ndim,
+                                    long sxy, double rh2) {
+  const double v = x[c];
+  const double xl = i > 0 ? x[c - 1] : v;
+  const double xr = i < nx - 1 ? x[c + 1] : v;
+  const double yl = j > 0 ? x[c - nx] : v;
+  const double yr = j < ny - 1 ? x[c + nx] : v;
+  double lap = (xl + xr - 2.0 * v) + (yl + yr - 2.0 * v);
+  if (ndim == 3) {
+    const double zl = k > 0 ? x[c - sxy] : v;
+    const double zr = k < nz - 1 ? x[c + sxy] : v;
+    lap += zl + zr - 2.0 * v;
+  }
+  return lap * rh2;
+}
+
+// mu = w'(phi') - gamma lap(phi'), w = sin^2(pi phi) / 64 (Eq. 2.15)
+template <typename T>
+__global__ __launch_bounds__(kBlock) void mu_kernel(PhaseArgs<T> A) {
+  const double rh2 = 1.0 / (A.h * A.h);
+  const double kPi = 3.141592653589793;
+  const long sxy = (long)A.nx * A.ny;
+  for (long c = (long)blockIdx.x * kBlock + threadIdx.x; c < A.n; c += (long)gridDim.x * kBlock) {
+    const int k = (int)(c / sxy);
+    const long rem = c - (long)k * sxy;
+    const int j = (int)(rem / A.nx), i = (int)(rem - (long)j * A.nx);
+    const double x = A.work[c];
+    const double wp = (kPi / 64.0) * sin(2.0 * kPi * x);
+    A.work2[c] = wp - A.gamma * lap_mirror(A.work, c, i, j, k, A.nx, A.ny, A.nz, A.ndim, sxy, rh2);
+  }
+}
+
+// phi = phi' + dt_ch D lap(mu); the new sum of the phase into the block partials
+template <typename T>
+__global__ __launch_bounds__(kBlock) void ch_kernel(PhaseArgs<T> A) {
+  __shared__ double red[kBlock / kWave];
+  const double rh2 = 1.0 / (A.h * A.h);
+  const long sxy = (long)A.nx * A.ny;
+  const double step = A.dt_ch * A.mobility;
+  double acc = 0.0;
+  for (long c = (long)blockIdx.x * kBlock + threadIdx.x; c < A.n; c += (long)gridDim.x * kBlock) {
+    const int k = (int)(c / sxy);
+    const long rem = c - (long)k * sxy;
+    const int j = (int)(rem / A.nx), i = (int)(rem - (long)j * A.nx);
+    const double y = A.work[c] + step * lap_mirror(A.work2, c, i, j, k, A.nx, A.ny, A.nz, A.ndim, sxy, rh2);
+    const T t = (T)y;
+    A.phi[c] = t;
+    acc += (double)t;
+  }
+  const double tot = block_sum(acc, red);
+  if (threadIdx.x == 0) A.partial[blockIdx.x] = tot;
+}
+
 }  // namespace
 
 int phase_blocks(long n) {
@@ -205,6 +304,32 @@ void launch_phase_apply(const PhaseArgs<T>& a, hipStream_t s) {
                      (double)a.n);
 }
 
+template <typename T>
+void launch_penalty_prep(const PhaseArgs<T>& a, hipStream_t s) {
+  launch_phase_gmax<T>(a, s);
+  hipLaunchKernelGGL((sum_kernel<T>), dim3(a.nblocks), dim3(kBlock), 0, s, a);
+  hipLaunchKernelGGL(sum_final_kernel, dim3(1), dim3(kWave), 0, s, a.partial, a.nblocks, a.scal);
+}
+
+template <typename T>
+void launch_penalty_step(const PhaseArgs<T>& a, hipStream_t s) {
+  hipLaunchKernelGGL((penalty_kernel<T>), dim3(a.nblocks), dim3(kBlock), 0, s, a);
+}
+
+template <typename T>
+void launch_cahn_hilliard(const PhaseArgs<T>& a, hipStream_t s) {
+  hipLaunchKernelGGL((mu_kernel<T>), dim3(a.nblocks), dim3(kBlock), 0, s, a);
+  hipLaunchKernelGGL((ch_kernel<T>), dim3(a.nblocks), dim3(kBlock), 0, s, a);
+  hipLaunchKernelGGL(volume_final_kernel, dim3(1), dim3(kWave), 0, s, a.partial, a.nblocks, a.scal,
+                     (double)a.n);
+}
+
+template void launch_penalty_prep<float>(const PhaseArgs<float>&, hipStream_t);
+template void launch_penalty_prep<double>(const PhaseArgs<double>&, hipStream_t);
+template void launch_penalty_step<float>(const PhaseArgs<float>&, hipStream_t);
+template void launch_penalty_step<double>(const PhaseArgs<double>&, hipStream_t);
+template void launch_cahn_hilliard<float>(const PhaseArgs<float>&, hipStream_t);
+template void launch_cahn_hilliard<double>(const PhaseArgs<double>&, hipStream_t);
 template void launch_phase_gmax<float>(const PhaseArgs<float>&, hipStream_t);
 template void launch_phase_gmax<double>(const PhaseArgs<double>&, hipStream_t);
 template void launch_phase_step<float>(const PhaseArgs<float>&, hipStream_t);
