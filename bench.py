@@ -53,6 +53,12 @@ def parse():
     ap.add_argument("--sweeps", type=int, default=2000, help="sweep-throughput legs: sweeps to time")
     ap.add_argument("--adapt", action="store_true",
                     help="re-choose the damping at every check from the state's Rayleigh quotient")
+    ap.add_argument("--schedule", default="tolerance", choices=["tolerance", "paper"],
+                    help="paper: the paper's loop (n_APT damped-wave + n_PT plain PT sweeps, penalty update, "
+                         "one Cahn-Hilliard step) in FP32, on the 2D cantilever or (--workload "
+                         "paper_heat2d_512) the paper's 2D heat set-up")
+    ap.add_argument("--n-apt", type=int, default=20)
+    ap.add_argument("--n-pt", type=int, default=20)
     ap.add_argument("--ttd-steps", type=int, default=0,
                     help="time to converged design: run this many design steps in FP32 (refined, graphs, "
                          "multi-sweep launches) and in FP64 (one sweep per launch, no graphs)")
@@ -252,6 +258,58 @@ def ttd_leg(args):
     print(json.dumps(out))
 
 
+def paper_leg(args):
+    """The paper's own loop on the 2D cantilever (FP32 sweeps, fixed counts): each
+    design step runs n_APT damped-wave and n_PT plain PT sweeps, the sensitivity,
+    the penalty update and one Cahn-Hilliard step."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2509_06971_amd.api import Context
+
+    if args.workload.startswith("paper_heat2d"):
+        n = int(args.workload.split("_")[-1]) if args.workload.split("_")[-1].isdigit() else 512
+        prob = W.paper_heat2d(n)
+        workload, family, bpc = prob.name, "heat", bytes_per_cell("heat")
+    else:
+        prob = W.cantilever2d(args.nx, args.ny)
+        workload, family, bpc = f"cantilever2d_{args.nx}x{args.ny}", "el2d", BYTES_PER_CELL_2D_FP32
+    ctx = Context(prob, "fp32")
+    phi = torch.tensor(W.initial_phi(prob).ravel(), dtype=torch.float32, device="cuda")
+    u = ctx.new_state()
+    v = ctx.new_state()
+    g = ctx.new_cells()
+    comp = torch.zeros(2, dtype=torch.float64, device="cuda")
+    ce = args.n_apt if args.n_apt % 2 == 0 else 2
+    apt = dict(theta=args.theta, replay_iters=args.n_apt, check_every=ce, n_pt=args.n_pt)
+    phase = dict(model="penalty")
+
+    def step():
+        ctx.step(phi, u, v, g, vol_frac=prob.vol_frac, compliance=comp, apt=apt, phase=phase)
+
+    for _ in range(max(args.warmup, 1)):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    sweeps = (args.n_apt + args.n_pt) * args.steps
+    out = {"metric": "APT cell-updates/s (paper schedule: design steps of n_APT + n_PT sweeps, penalty update, "
+                     "Cahn-Hilliard step)",
+           "value": prob.ncell * sweeps / wall, "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": 1000.0 * wall / args.steps, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": workload, "cells": prob.ncell, "n_apt": args.n_apt,
+                      "n_pt": args.n_pt, "theta": args.theta, "compliance": comp[0].item(),
+                      "mean_phi": float(phi.double().mean().item())}}
+    out["roofline"] = kernel_roofline(ctx, bpc * prob.ncell, family, workload)
+    ctx.close()
+    print(json.dumps(out))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -260,6 +318,9 @@ def main():
         sys.exit(2)
     if args.ttd_steps > 0:
         ttd_leg(args)
+        return
+    if args.schedule == "paper":
+        paper_leg(args)
         return
     if args.workload != "cantilever2d":
         sweep_leg(args)

@@ -332,12 +332,14 @@ petto_status enqueue_block(petto_ctx* c, hipStream_t stream, bool use_graph, con
 // kept in flight; a block enqueued after the stop finds the done flags set and its
 // kernels return at once.  Blocks timed (when enabled) are those up to the stop.
 petto_status run_blocks(petto_ctx* c, hipStream_t stream, bool use_graph, const std::vector<const void*>& key,
-                        const std::function<void(hipStream_t)>& body, int sweeps_per_block, PollRecord* last) {
+                        const std::function<void(hipStream_t)>& body, int sweeps_per_block, PollRecord* last,
+                        long max_blocks) {
   PETTO_TRY(ensure_events(c));
   long launched = 0, checked = 0;
   std::vector<float> block_ms;
   for (;;) {
-    while (launched - checked < 2) {
+    // never more blocks than the stop rule can use (fixed counts: exactly that many)
+    while (launched - checked < 2 && launched < max_blocks) {
       if (c->timing) HIP_TRY(hipEventRecord(c->ev_beg[launched % kRing], stream));
       PETTO_TRY(enqueue_block(c, stream, use_graph, key, body));
       HIP_TRY(hipEventRecord(c->ev_end[launched % kRing], stream));
@@ -357,7 +359,7 @@ petto_status run_blocks(petto_ctx* c, hipStream_t stream, bool use_graph, const 
       c->timed_sweeps += sweeps_per_block;
     }
     ++checked;
-    if (rec.all_done) {
+    if (rec.all_done || checked == max_blocks) {
       *last = rec;
       break;
     }
@@ -696,7 +698,9 @@ petto_status solve_plain(petto_ctx* c, const void* phi, void* u, void* v, const 
   std::vector<const void*> key = {uu, ua, vv, E, b, (const void*)(long)nchk, (const void*)(long)sizeof(T),
                                   (const void*)1, (const void*)(long)block_k(c, nchk), (const void*)(long)adapt};
   PollRecord last{};
-  PETTO_TRY(run_blocks(c, s, ap->use_graph != 0, key, body, nchk, &last));
+  // the finalize of the last block marks the stop at max_iter (replay: exactly there)
+  const long max_blocks = replay ? ap->replay_iters / nchk : ((long)ap->max_iter + nchk - 1) / nchk;
+  PETTO_TRY(run_blocks(c, s, ap->use_graph != 0, key, body, nchk, &last, max_blocks));
   std::vector<SolveState> h;
   PETTO_TRY(read_states(c, c->st, h, s));
   if (info) {
@@ -770,7 +774,10 @@ petto_status solve_refine(petto_ctx* c, const void* phi, void* u, void* v, const
   std::vector<const void*> key = {u64, da, db, v32, E, b, (const void*)(long)nchk, (const void*)2,
                                   (const void*)(long)block_k(c, nchk), (const void*)(long)adapt};
   PollRecord last{};
-  PETTO_TRY(run_blocks(c, s, ap->use_graph != 0, key, body, nchk, &last));
+  // a block checks the state its predecessors produced: one block more than the
+  // sweeps need, for the check that stops at max_iter
+  const long max_blocks = ((long)ap->max_iter + nchk - 1) / nchk + 1;
+  PETTO_TRY(run_blocks(c, s, ap->use_graph != 0, key, body, nchk, &last, max_blocks));
   std::vector<SolveState> h;
   PETTO_TRY(read_states(c, c->st, h, s));
   if (info) {

@@ -137,3 +137,19 @@ def test_paper_schedule_trajectory_fp64():
         assert rel_l2(host(phi, phi_np.shape), phi_np) < 1e-10, step
         assert comp[0].item() == pytest.approx(C, rel=1e-10), step
     ctx.close()
+
+
+def test_hybrid_schedule_heat_parity():
+    """The paper's 2D heat set-up (small grid): 60 damped-wave + 40 PT sweeps, FP64."""
+    require_gpu()
+    prob = W.paper_heat2d(40)
+    announce("hybrid schedule paper heat 40x40")
+    phi = W.random_phi(prob, 2, 0.1, 1.0)
+    ctx = context(prob, "fp64")
+    u = ctx.new_state()
+    v = ctx.new_state()
+    st, info = ctx.solve(dev(phi, torch.float64), u, v, theta=1.0, replay_iters=60, check_every=20, n_pt=40)
+    want, iters, rho = pv.hybrid_solve(phi, prob, None, n_apt=60, n_pt=40, theta=1.0, check_every=20)
+    assert info[0]["iters"] == iters == 100
+    assert rel_l2(host(u, prob.cell_shape()), want) < 1e-12
+    ctx.close()

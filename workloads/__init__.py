@@ -284,6 +284,19 @@ def manufactured_heat(n, k=1.0):
     return prob, phi, Tex
 
 
+def paper_heat2d(n=512, kmin=1e-6, q=0.01):
+    """The paper's 2D single-material heat set-up (Section 3.1): an n x n grid,
+    T = 0 on the top and left sides, no flux on the right and bottom, a uniform
+    source f = 0.01, void conductivity 1e-6, target solid fraction 0.3; h = 1/n
+    (the printed grid size)."""
+    fixed = np.zeros((n, n), dtype=np.uint8)
+    fixed[:, 0] |= 1          # left side (x = 0)
+    fixed[n - 1, :] |= 8      # top side (y = L)
+    prob = Problem(HEAT, 2, (n, n), 1.0 / n, 1.0, kmin, 0.0, 3.0, (FREE,) * 6, fixed, None, q=q,
+                   vol_frac=(0.3,), name=f"paper_heat2d_{n}")
+    return prob
+
+
 def heat_batch(ndesign=64, lo=128, hi=1024, seed=0, kmin=1e-3, q=1.0):
     """Batch of independent 2D heat designs of uneven size.
 
