@@ -60,10 +60,13 @@ enum { PETTO_FP32 = 0, PETTO_FP64 = 1 };
 enum { PETTO_SIDE_FREE = 0, PETTO_SIDE_CLAMPED = 1, PETTO_SIDE_ROLLER = 2 };
 enum { PETTO_FIELD_STATE = 0, PETTO_FIELD_CELL = 1 };
 
+#define PETTO_MAX_PHASES 6
+
 /* One design problem (Section 2.1).  Material law: single phase uses the modified
- * SIMP form  E = emin + phi^p (e0 - emin)  (heat: k, same form); nphase = 2 stores
- * two solid phases and E = e_phase[0] phi1^p + e_phase[1] phi2^p + e_phase[2] (1-phi1-phi2)^p
- * (Eq. 3.8 with an implicit void phase).  Elastic 2D uses the Lame parameters of
+ * SIMP form  E = emin + phi^p (e0 - emin)  (heat: k, same form); nphase = N in
+ * 2..PETTO_MAX_PHASES stores N solid phases and
+ * E = sum_m e_phase[m] phi_m^p + e_phase[N] (1 - sum_m phi_m)^p (Eq. 3.8 with an
+ * implicit void phase).  Fractions enter the laws clamped to [0, 1].  Elastic 2D uses the Lame parameters of
  * Eq. 3.10 as printed (plane strain).
  *  side[6]: boundary type of the -x,+x,-y,+y,-z,+z sides.  CLAMPED fixes both
  *           components (normal unknown zero, tangential reflected); ROLLER fixes the
@@ -81,8 +84,8 @@ typedef struct {
   int32_t n[3];             /* cells along x, y, z (n[2] ignored in 2D) */
   double h;                 /* grid spacing */
   double e0, emin, nu, p;   /* SIMP law; nu ignored for heat */
-  int32_t nphase;           /* 1, or 2 (elastic only) */
-  double e_phase[3];        /* nphase == 2: phase 1, phase 2, void */
+  int32_t nphase;           /* 1, or 2..PETTO_MAX_PHASES (elastic only) */
+  double e_phase[PETTO_MAX_PHASES + 1];  /* nphase >= 2: the solid phases, then the void */
   int32_t side[6];
   const uint8_t *fixed;
   const double *load;
@@ -131,8 +134,8 @@ enum { PETTO_UPDATE_ALLEN_CAHN = 0, PETTO_UPDATE_PENALTY_CH = 1 };
  * (Eq. 3.2 step), phi'' = phi' - dt_ac (w'(phi') - gamma lap phi') with
  * w = sin^2(pi phi)/64 (Eq. 2.15) and mirror boundaries, then
  * phi = clamp(phi'' + s, 0, ub) with s such that mean(phi) = vol_frac (ub = 1 for
- * the first phase, 1 - phi1 for the second).  dt_ac <= 0 selects
- * 0.9 min(h^2 / (4 d gamma), 32 / pi^2).  bisect_passes <= 0 selects the default
+ * the first phase, 1 minus the already updated phases for the later ones).
+ * dt_ac <= 0 selects 0.9 min(h^2 / (4 d gamma), 32 / pi^2).  bisect_passes <= 0 selects the default
  * (9 passes of a 64-way bracket split, bracket width <= 2^-54 of the start).
  * model PETTO_UPDATE_PENALTY_CH (the paper's own update, Eq. 2.13 with the
  * normalised sensitivity of Section 3.1, then one explicit step of Eq. 2.14):
@@ -146,7 +149,7 @@ typedef struct {
   double alpha_h;
   double gamma;
   double dt_ac;
-  double vol_frac[2];
+  double vol_frac[PETTO_MAX_PHASES];
   int32_t bisect_passes;
   int32_t model;            /* PETTO_UPDATE_ALLEN_CAHN (above) or PETTO_UPDATE_PENALTY_CH */
   double alpha_v;           /* penalty model: volume-penalty weight (paper: 1e5) */
@@ -167,9 +170,9 @@ typedef struct {
 } petto_solve_info;
 
 typedef struct {
-  double shift[2];          /* volume multiplier s per phase (penalty model: -alpha_v dJ_v/dphi) */
-  double volume[2];         /* mean(phi) per phase after the update */
-  double gmax[2];           /* max |g| per phase used for normalisation */
+  double shift[PETTO_MAX_PHASES];   /* volume multiplier s per phase (penalty model: -alpha_v dJ_v/dphi) */
+  double volume[PETTO_MAX_PHASES];  /* mean(phi) per phase after the update */
+  double gmax[PETTO_MAX_PHASES];    /* max |g| per phase used for normalisation */
 } petto_phase_info;
 
 /* Create a context for nprob designs in precision prec (PETTO_FP32 / PETTO_FP64).

@@ -20,11 +20,14 @@ STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", -1: "ERR_INVALID", -2: "ERR_HIP", -
                 -4: "ERR_OOM", -5: "ERR_UNSUPPORTED"}
 
 
+MAX_PHASES = 6          # PETTO_MAX_PHASES of the header
+
+
 class Problem(C.Structure):
     _fields_ = [
         ("physics", C.c_int32), ("ndim", C.c_int32), ("n", C.c_int32 * 3), ("h", C.c_double),
         ("e0", C.c_double), ("emin", C.c_double), ("nu", C.c_double), ("p", C.c_double),
-        ("nphase", C.c_int32), ("e_phase", C.c_double * 3), ("side", C.c_int32 * 6),
+        ("nphase", C.c_int32), ("e_phase", C.c_double * (MAX_PHASES + 1)), ("side", C.c_int32 * 6),
         ("fixed", C.POINTER(C.c_uint8)), ("load", C.POINTER(C.c_double)), ("q", C.c_double),
     ]
 
@@ -40,7 +43,7 @@ class AptParams(C.Structure):
 class PhaseParams(C.Structure):
     _fields_ = [
         ("alpha_h", C.c_double), ("gamma", C.c_double), ("dt_ac", C.c_double),
-        ("vol_frac", C.c_double * 2), ("bisect_passes", C.c_int32), ("model", C.c_int32),
+        ("vol_frac", C.c_double * MAX_PHASES), ("bisect_passes", C.c_int32), ("model", C.c_int32),
         ("alpha_v", C.c_double), ("alpha_1", C.c_double), ("dt_ch", C.c_double), ("mobility", C.c_double),
     ]
 
@@ -56,7 +59,8 @@ class SolveInfo(C.Structure):
 
 
 class PhaseInfo(C.Structure):
-    _fields_ = [("shift", C.c_double * 2), ("volume", C.c_double * 2), ("gmax", C.c_double * 2)]
+    _fields_ = [("shift", C.c_double * MAX_PHASES), ("volume", C.c_double * MAX_PHASES),
+                ("gmax", C.c_double * MAX_PHASES)]
 
     def as_dict(self):
         return {"shift": list(self.shift), "volume": list(self.volume), "gmax": list(self.gmax)}

@@ -20,8 +20,8 @@ def _problem_struct(p, keep):
     s.h = float(p.h)
     s.e0, s.emin, s.nu, s.p = float(p.e0), float(p.emin), float(p.nu), float(p.p)
     s.nphase = int(getattr(p, "nphase", 1))
-    ep = list(getattr(p, "e_phase", ())) + [0.0] * 3
-    for m in range(3):
+    ep = list(getattr(p, "e_phase", ())) + [0.0] * (L.MAX_PHASES + 1)
+    for m in range(L.MAX_PHASES + 1):
         s.e_phase[m] = float(ep[m])
     side = list(getattr(p, "side", (0,) * 6)) + [0] * 6
     for k in range(6):
@@ -109,8 +109,9 @@ class Context:
         "penalty" (the paper's penalty update + one Cahn-Hilliard step)."""
         p = L.PhaseParams()
         p.alpha_h, p.gamma, p.dt_ac = float(alpha_h), float(gamma), float(dt_ac)
-        vf = list(vol_frac) + [0.0, 0.0]
-        p.vol_frac[0], p.vol_frac[1] = float(vf[0]), float(vf[1])
+        vf = list(vol_frac) + [0.0] * L.MAX_PHASES
+        for m in range(L.MAX_PHASES):
+            p.vol_frac[m] = float(vf[m])
         p.bisect_passes = int(bisect_passes)
         p.model = {"allen_cahn": 0, "penalty": 1}[model]
         p.alpha_v, p.alpha_1, p.dt_ch, p.mobility = float(alpha_v), float(alpha_1), float(dt_ch), float(mobility)

@@ -10,7 +10,8 @@ constexpr int kWave = 64;           // CDNA wavefront width
 constexpr int kNumXcd = 8;          // MI355X accelerator complex dies (one L2 each)
 constexpr int kMaxDesigns = 1024;   // upper bound of a batch
 constexpr int kCand = 63;           // candidate shifts per volume-bracket pass
-constexpr int kRing = 8;            // status ring slots polled by the host
+constexpr int kRing = 8;             // status ring slots polled by the host
+constexpr int kMaxPhase = 6;         // stored solid phases (PETTO_MAX_PHASES)
 
 // Solve bookkeeping of one design, resident in device memory.  Written by the
 // setup / finalize kernels, read by every sweep (coefficients, stop flag).

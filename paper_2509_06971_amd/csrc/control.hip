@@ -9,19 +9,23 @@
 namespace petto {
 namespace {
 
+struct PhaseModuli {
+  double e[kMaxPhase + 1];  // solid phases, then the void
+};
+
 template <typename T>
 __global__ __launch_bounds__(kBlock) void material_kernel(const T* __restrict__ phi, T* __restrict__ E,
                                                           double* __restrict__ E64, const CellRange* ranges,
                                                           int nphase, long phase_stride, double e0,
-                                                          double emin, double p, double ep0, double ep1,
-                                                          double ep2, double* partial_max, int bpd) {
+                                                          double emin, double p, PhaseModuli pm,
+                                                          double* partial_max, int bpd) {
   __shared__ double red[kBlock / kWave];
   const int d = blockIdx.y;
   const CellRange R = ranges[d];
-  const double ep[3] = {ep0, ep1, ep2};
+  const double* ep = pm.e;
   double mx = 0.0;
   for (long c = (long)blockIdx.x * kBlock + threadIdx.x; c < R.n; c += (long)gridDim.x * kBlock) {
-    double dE[2];
+    double dE[kMaxPhase];
     const double e = modulus<T>(phi, R.off + c, phase_stride, nphase, e0, emin, p, ep, dE);
     E[R.off + c] = (T)e;
     if (E64 != nullptr) E64[R.off + c] = e;
@@ -234,9 +238,10 @@ void launch_material(const T* phi, T* E, double* E64, const CellRange* ranges, i
                      int nphase, long phase_stride, double e0, double emin, double p, const double* ep,
                      double* partial_max, int blocks_per_design, hipStream_t s) {
   (void)max_cells;
+  PhaseModuli pm{};
+  for (int m = 0; m <= nphase && m <= kMaxPhase; ++m) pm.e[m] = ep[m];
   hipLaunchKernelGGL((material_kernel<T>), dim3(blocks_per_design, ndes), dim3(kBlock), 0, s, phi, E, E64,
-                     ranges, nphase, phase_stride, e0, emin, p, ep[0], ep[1], ep[2], partial_max,
-                     blocks_per_design);
+                     ranges, nphase, phase_stride, e0, emin, p, pm, partial_max, blocks_per_design);
 }
 
 template <typename U, typename R>

@@ -268,7 +268,7 @@ __global__ __launch_bounds__(kBlock) void el2d_adjoint_kernel(ElGeom g, ElAdjoin
     Buu *= hd;
     Bwu *= hd;
     const long c = (long)j * nx + i;
-    double dE[2];
+    double dE[kMaxPhase];
     const double E = modulus<T>(A.phi, c, ncell, A.nphase, A.e0, A.emin, A.p, A.ep, dE);
     en += E * Buu;
     for (int m = 0; m < A.nphase; ++m) A.grad[m * ncell + c] = (T)(-dE[m] * Bwu);

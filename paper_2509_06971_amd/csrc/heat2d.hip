@@ -159,7 +159,7 @@ __global__ __launch_bounds__(kBlock) void heat2d_adjoint_kernel(HeatAdjoint<U, T
     const int nd = (i == 0 || j == 0 || i == D.nx - 1 || j == D.ny - 1) ? dirichlet_count(D, A.dir, i, j) : 0;
     Buu += 2.0 * nd * tu * tu;
     Bwu += 2.0 * nd * tw * tu;
-    double dE[2];
+    double dE[kMaxPhase];
     const double k = modulus<T>(A.phi, c, 0, 1, A.e0, A.emin, A.p, ep_dummy, dE);
     en += k * Buu;
     A.grad[c] = (T)(-dE[0] * Bwu);

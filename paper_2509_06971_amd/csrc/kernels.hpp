@@ -63,7 +63,7 @@ struct ElAdjoint {
   double* partial_en;       // per tile
   int nphase;
   double e0, emin, p;
-  double ep[3];
+  double ep[kMaxPhase + 1];   // solid phases, then the void
 };
 template <typename U, typename T>
 int launch_el2d_adjoint(const ElGeom& g, const ElAdjoint<U, T>& a, hipStream_t s);
@@ -197,7 +197,9 @@ template <typename T>
 struct PhaseArgs {
   T* phi;                   // phase m of the design (in/out)
   const T* g;               // sensitivity of phase m
-  const T* prev;            // earlier phase (upper bound 1 - prev), or nullptr (bound 1)
+  double* used;             // sum of the phases updated before this one (upper bound
+                            // 1 - used), or nullptr (bound 1)
+  double* used_out;         // apply: receives used + the new phase, or nullptr
   double* work;             // phi'' of this design (double)
   double* partial;          // per block scratch, >= nblocks * 64
   double* scal;             // [0] gmax [1] lo [2] hi [3] s [4] mean phi [5] target sum
@@ -207,7 +209,7 @@ struct PhaseArgs {
   double h, alpha, gamma, dt_ac, target;
   int nblocks;
   // the penalty / Cahn-Hilliard update
-  const T* other;           // the other stored phase (partition sum), or nullptr
+  const double* total;      // sum of all stored phases of the old design, or nullptr (this phase alone)
   double* work2;            // chemical potential mu (double)
   double alpha_v, alpha_1, vol_frac, dt_ch, mobility;
 };
@@ -222,6 +224,9 @@ int phase_blocks(long n);
 template <typename T> void launch_penalty_prep(const PhaseArgs<T>& a, hipStream_t s);
 template <typename T> void launch_penalty_step(const PhaseArgs<T>& a, hipStream_t s);
 template <typename T> void launch_cahn_hilliard(const PhaseArgs<T>& a, hipStream_t s);
+// total[c] = sum over nphase stored phases (stride ncell) of phi[c]
+template <typename T>
+void launch_phase_total(const T* phi, long ncell, int nphase, long n, double* total, hipStream_t s);
 
 // out[2d] = sum of pfu over design d's tiles, out[2d+1] = the same for pen.
 void launch_dot_finalize(const double* pfu, const double* pen, const int* tile0, int ntile, int ndes,

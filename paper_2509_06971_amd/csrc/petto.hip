@@ -110,7 +110,8 @@ struct petto_ctx {
   double* phase_scal = nullptr;
   double* phase_work = nullptr;
   double* phase_partial = nullptr;
-  double* pen_work = nullptr;          // penalty update: phi' per phase and mu ((nphase + 1) x cells)
+  double* pen_work = nullptr;          // penalty update: phi' per phase, mu, partition sum
+  double* phase_used = nullptr;        // Allen-Cahn update: sum of the phases already updated
   double* comp = nullptr;
   hipStream_t cap_stream = nullptr;
   hipEvent_t ev_end[kRing] = {};
@@ -183,14 +184,16 @@ petto_status validate_problem(const petto_problem& p, int idx) {
       return fail(PETTO_ERR_INVALID, "problem %d: n[%d]=%d outside [2, 65536]", idx, a, p.n[a]);
   }
   if (!(p.h > 0.0) || !is_finite(p.h)) return fail(PETTO_ERR_INVALID, "problem %d: h must be positive", idx);
-  if (p.nphase != 1 && p.nphase != 2) return fail(PETTO_ERR_INVALID, "problem %d: nphase must be 1 or 2", idx);
+  if (p.nphase < 1 || p.nphase > kMaxPhase)
+    return fail(PETTO_ERR_INVALID, "problem %d: nphase must be in [1, %d]", idx, kMaxPhase);
   if (!(p.p >= 1.0) || !is_finite(p.p)) return fail(PETTO_ERR_INVALID, "problem %d: penalty p must be >= 1", idx);
   if (p.nphase == 1) {
     if (!(p.e0 > 0.0) || !(p.emin >= 0.0) || !(p.emin < p.e0) || !is_finite(p.e0))
       return fail(PETTO_ERR_INVALID, "problem %d: need 0 <= emin < e0", idx);
   } else {
-    if (p.physics != PETTO_ELASTIC) return fail(PETTO_ERR_INVALID, "problem %d: nphase 2 is elastic only", idx);
-    for (int m = 0; m < 3; ++m)
+    if (p.physics != PETTO_ELASTIC)
+      return fail(PETTO_ERR_INVALID, "problem %d: several phases are elastic only", idx);
+    for (int m = 0; m <= p.nphase; ++m)
       if (!(p.e_phase[m] >= 0.0) || !is_finite(p.e_phase[m]))
         return fail(PETTO_ERR_INVALID, "problem %d: e_phase[%d] must be >= 0", idx, m);
     if (!(p.e_phase[0] > 0.0)) return fail(PETTO_ERR_INVALID, "problem %d: e_phase[0] must be > 0", idx);
@@ -541,8 +544,8 @@ void finalize(const petto_ctx* c, hipStream_t s, SolveState* st, const int* tile
 
 template <typename T>
 petto_status material(petto_ctx* c, const void* phi, hipStream_t s, bool with64) {
-  const double ep[3] = {c->probs[0].e_phase[0], c->probs[0].e_phase[1], c->probs[0].e_phase[2]};
   const petto_problem& p = c->probs[0];
+  const double* ep = p.e_phase;
   launch_material<T>(static_cast<const T*>(phi), static_cast<T*>(c->E), with64 ? c->E64 : nullptr, c->d_ranges,
                      c->nprob, c->max_cells, c->nphase, c->ncell, p.e0, p.emin, p.p, ep, c->partial_max, kBpd, s);
   HIP_TRY(hipGetLastError());
@@ -811,7 +814,7 @@ int adjoint_launch(petto_ctx* c, const void* phi, const void* u, const void* w, 
     a.e0 = p.e0;
     a.emin = p.emin;
     a.p = p.p;
-    for (int m = 0; m < 3; ++m) a.ep[m] = p.e_phase[m];
+    for (int m = 0; m <= kMaxPhase; ++m) a.ep[m] = p.e_phase[m];
     return c->ndim == 2 ? launch_el2d_adjoint<U, T>(c->geom, a, s) : launch_el3d_adjoint<U, T>(c->geom, a, s);
   } else {
     HeatAdjoint<U, T> a{};
@@ -841,20 +844,24 @@ petto_status phase_update_impl(petto_ctx* c, void* phi, const void* grad, const 
   const T* g = static_cast<const T*>(grad);
   const int passes = pp->bisect_passes > 0 ? pp->bisect_passes : 9;
   if (pp->model == PETTO_UPDATE_PENALTY_CH) {
-    if (c->pen_work == nullptr) PETTO_TRY(dalloc_t(c, &c->pen_work, (size_t)(c->nphase + 1) * c->max_cells));
+    // per phase phi', then mu, then the partition sum of the old design
+    if (c->pen_work == nullptr) PETTO_TRY(dalloc_t(c, &c->pen_work, (size_t)(c->nphase + 2) * c->max_cells));
+    double* total = c->pen_work + (long)(c->nphase + 1) * c->max_cells;
     for (int d = 0; d < c->nprob; ++d) {
       const CellRange& R = c->h_ranges[d];
       const double h = R.h;
+      const bool partition = pp->alpha_1 != 0.0 && c->nphase > 1;
+      if (partition) launch_phase_total<T>(ph + R.off, c->ncell, c->nphase, R.n, total, s);
       std::vector<PhaseArgs<T>> args(c->nphase);
       for (int m = 0; m < c->nphase; ++m) {
         PhaseArgs<T>& a = args[m];
         a.phi = ph + (long)m * c->ncell + R.off;
         a.g = g + (long)m * c->ncell + R.off;
-        a.other = c->nphase == 2 ? ph + (long)(1 - m) * c->ncell + R.off : nullptr;
+        a.total = partition ? total : nullptr;
         a.work = c->pen_work + (long)m * c->max_cells;
         a.work2 = c->pen_work + (long)c->nphase * c->max_cells;
         a.partial = c->phase_partial;
-        a.scal = c->phase_scal + (long)(2 * d + m) * 8;
+        a.scal = c->phase_scal + (long)(kMaxPhase * d + m) * 8;
         a.nx = R.nx;
         a.ny = R.ny;
         a.nz = R.nz;
@@ -879,6 +886,7 @@ petto_status phase_update_impl(petto_ctx* c, void* phi, const void* grad, const 
       HIP_TRY(hipGetLastError());
     }
   } else {
+  if (c->nphase > 1 && c->phase_used == nullptr) PETTO_TRY(dalloc_t(c, &c->phase_used, c->max_cells));
   for (int d = 0; d < c->nprob; ++d) {
     const CellRange& R = c->h_ranges[d];
     const double h = R.h;
@@ -892,10 +900,12 @@ petto_status phase_update_impl(petto_ctx* c, void* phi, const void* grad, const 
       PhaseArgs<T> a{};
       a.phi = ph + (long)m * c->ncell + R.off;
       a.g = g + (long)m * c->ncell + R.off;
-      a.prev = m == 0 ? nullptr : ph + R.off;
+      // later phases are bounded by what the earlier ones (already updated) leave
+      a.used = m == 0 ? nullptr : c->phase_used;
+      a.used_out = m + 1 < c->nphase ? c->phase_used : nullptr;
       a.work = c->phase_work;
       a.partial = c->phase_partial;
-      a.scal = c->phase_scal + (long)(2 * d + m) * 8;
+      a.scal = c->phase_scal + (long)(kMaxPhase * d + m) * 8;
       a.nx = R.nx;
       a.ny = R.ny;
       a.nz = R.nz;
@@ -916,12 +926,12 @@ petto_status phase_update_impl(petto_ctx* c, void* phi, const void* grad, const 
   }
   }
   if (info) {
-    std::vector<double> sc((size_t)c->nprob * 16);
+    std::vector<double> sc((size_t)c->nprob * kMaxPhase * 8);
     HIP_TRY(hipMemcpyAsync(sc.data(), c->phase_scal, sizeof(double) * sc.size(), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     for (int d = 0; d < c->nprob; ++d) {
-      for (int m = 0; m < 2; ++m) {
-        const double* q = sc.data() + (2 * d + m) * 8;
+      for (int m = 0; m < kMaxPhase; ++m) {
+        const double* q = sc.data() + (kMaxPhase * d + m) * 8;
         info[d].gmax[m] = m < c->nphase ? q[0] : 0.0;
         info[d].shift[m] = m < c->nphase ? q[3] : 0.0;
         info[d].volume[m] = m < c->nphase ? q[4] : 0.0;
@@ -1161,7 +1171,7 @@ petto_status petto_create(const petto_problem* probs, int32_t nprob, int32_t pre
     void* rd = nullptr;
     HIP_TRY(hipHostGetDevicePointer(&rd, ring, 0));
     c->ring_dev = static_cast<PollRecord*>(rd);
-    PETTO_TRY(dalloc_t(c, &c->phase_scal, (size_t)nprob * 16));
+    PETTO_TRY(dalloc_t(c, &c->phase_scal, (size_t)nprob * kMaxPhase * 8));
     PETTO_TRY(dalloc_t(c, &c->phase_work, c->max_cells));
     PETTO_TRY(dalloc_t(c, &c->phase_partial, (size_t)phase_blocks(c->max_cells) * (kCand + 1) + 64));
     PETTO_TRY(dalloc_t(c, &c->comp, (size_t)2 * nprob));

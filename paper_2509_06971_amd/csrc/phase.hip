@@ -46,7 +46,7 @@ __global__ __launch_bounds__(kBlock) void step_kernel(PhaseArgs<T> A) {
   const double gmax = A.scal[0];
   const double rh2 = 1.0 / (A.h * A.h);
   const double kPi = 3.141592653589793;
-  double mn = INFINITY, mx = -INFINITY, ubmax = (A.prev == nullptr) ? 1.0 : -INFINITY;
+  double mn = INFINITY, mx = -INFINITY, ubmax = (A.used == nullptr) ? 1.0 : -INFINITY;
   const long sxy = (long)A.nx * A.ny;
   for (long c = (long)blockIdx.x * kBlock + threadIdx.x; c < A.n; c += (long)gridDim.x * kBlock) {
     const int k = (int)(c / sxy);
@@ -70,7 +70,7 @@ __global__ __launch_bounds__(kBlock) void step_kernel(PhaseArgs<T> A) {
     A.work[c] = y;
     mn = fmin(mn, y);
     mx = fmax(mx, y);
-    if (A.prev != nullptr) ubmax = fmax(ubmax, 1.0 - (double)A.prev[c]);
+    if (A.used != nullptr) ubmax = fmax(ubmax, 1.0 - A.used[c]);
   }
   const double a = block_min(mn, red);
   const double b = block_max(mx, red);
@@ -110,7 +110,7 @@ __global__ __launch_bounds__(kBlock) void pass_kernel(PhaseArgs<T> A) {
   for (int k = 0; k < kCand; ++k) acc[k] = 0.0;
   for (long c = (long)blockIdx.x * kBlock + threadIdx.x; c < A.n; c += (long)gridDim.x * kBlock) {
     const double x = A.work[c];
-    const double ub = A.prev == nullptr ? 1.0 : 1.0 - (double)A.prev[c];
+    const double ub = A.used == nullptr ? 1.0 : 1.0 - A.used[c];
 #pragma unroll
     for (int k = 0; k < kCand; ++k) acc[k] += fmin(fmax(x + (lo + (k + 1) * step), 0.0), ub);
   }
@@ -159,10 +159,11 @@ __global__ __launch_bounds__(kBlock) void apply_kernel(PhaseArgs<T> A) {
   const double s = 0.5 * (A.scal[1] + A.scal[2]);
   double acc = 0.0;
   for (long c = (long)blockIdx.x * kBlock + threadIdx.x; c < A.n; c += (long)gridDim.x * kBlock) {
-    const double ub = A.prev == nullptr ? 1.0 : 1.0 - (double)A.prev[c];
+    const double ub = A.used == nullptr ? 1.0 : 1.0 - A.used[c];
     const T y = (T)fmin(fmax(A.work[c] + s, 0.0), ub);
     A.phi[c] = y;
     acc += (double)y;
+    if (A.used_out != nullptr) A.used_out[c] = (A.used == nullptr ? 0.0 : A.used[c]) + (double)y;
   }
   const double t = block_sum(acc, red);
   if (threadIdx.x == 0) A.partial[blockIdx.x] = t;
@@ -209,7 +210,7 @@ __global__ __launch_bounds__(kBlock) void penalty_kernel(PhaseArgs<T> A) {
     const double gh = gmax > 0.0 ? (double)A.g[c] / gmax : 0.0;
     double y = (f - A.alpha * gh) - vpen;
     if (A.alpha_1 != 0.0) {
-      const double tot = A.other != nullptr ? f + (double)A.other[c] : f;
+      const double tot = A.total != nullptr ? A.total[c] : f;
       y = y - A.alpha_1 * (2.0 * (tot - 1.0) * hd);
     }
     A.work[c] = y;
@@ -271,7 +272,23 @@ __global__ __launch_bounds__(kBlock) void ch_kernel(PhaseArgs<T> A) {
   if (threadIdx.x == 0) A.partial[blockIdx.x] = tot;
 }
 
+template <typename T>
+__global__ __launch_bounds__(kBlock) void total_kernel(const T* phi, long ncell, int nphase, long n, double* total) {
+  for (long c = (long)blockIdx.x * kBlock + threadIdx.x; c < n; c += (long)gridDim.x * kBlock) {
+    double t = 0.0;
+    for (int m = 0; m < nphase; ++m) t += (double)phi[c + m * ncell];
+    total[c] = t;
+  }
+}
+
 }  // namespace
+
+template <typename T>
+void launch_phase_total(const T* phi, long ncell, int nphase, long n, double* total, hipStream_t s) {
+  hipLaunchKernelGGL((total_kernel<T>), dim3(phase_blocks(n)), dim3(kBlock), 0, s, phi, ncell, nphase, n, total);
+}
+template void launch_phase_total<float>(const float*, long, int, long, double*, hipStream_t);
+template void launch_phase_total<double>(const double*, long, int, long, double*, hipStream_t);
 
 int phase_blocks(long n) {
   long b = (n + kBlock - 1) / kBlock;

@@ -18,6 +18,12 @@ def lib():
     return L.load()
 
 
+def test_phase_count_matches_header():
+    import re
+    txt = open(L.HEADER).read()
+    assert int(re.search(r"#define PETTO_MAX_PHASES (\d+)", txt).group(1)) == L.MAX_PHASES
+
+
 def test_exports_every_declared_symbol(lib):
     declared = L.declared_functions()
     assert len(declared) >= 12

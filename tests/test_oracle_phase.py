@@ -87,6 +87,19 @@ def test_volume_and_simplex_two_phases():
     assert out.min() >= 0.0 and (out[0] + out[1]).max() <= 1.0 + 1e-15
 
 
+def test_volume_and_simplex_five_phases():
+    """Five solid phases, each bounded by what the earlier ones leave: every
+    volume exact, fractions in [0, 1], their sum at most 1."""
+    prob = W.mbb2d(16, 8)
+    rng = np.random.default_rng(5)
+    phi = W.random_phi(prob, 6, 0.0, 0.4)
+    g = -rng.random(phi.shape)
+    out, info = design.phase_update(phi, g, prob)
+    for m in range(5):
+        assert np.mean(out[m]) == pytest.approx(0.08, abs=1e-12)
+    assert out.min() >= 0.0 and out.sum(axis=0).max() <= 1.0 + 1e-12
+
+
 def test_default_allen_cahn_step_is_stable():
     """dt (4 d gamma / h^2 + max w'') stays below 2 for the default step."""
     for h, nd in ((1 / 32, 2), (1 / 512, 2), (1 / 64, 3), (1 / 128, 3)):

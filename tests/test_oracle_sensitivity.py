@@ -18,11 +18,12 @@ def _problems():
     p3 = W.cantilever3d(5, 4, 4)
     pm = W.multimaterial3d(6, 4, 4)
     probs, phis, _ = W.heat_batch(1, 9, 13, seed=11)
+    p5 = W.mbb2d(12, 4)
     return [(p2, W.random_phi(p2, 1, 0.05, 1.0)), (p3, W.random_phi(p3, 2, 0.05, 1.0)),
-            (pm, W.random_phi(pm, 3, 0.05, 0.5)), (probs[0], phis[0])]
+            (pm, W.random_phi(pm, 3, 0.05, 0.5)), (probs[0], phis[0]), (p5, W.random_phi(p5, 4, 0.02, 0.3))]
 
 
-@pytest.mark.parametrize("case", range(4))
+@pytest.mark.parametrize("case", range(5))
 def test_euler_homogeneity(case):
     """C is homogeneous of degree -1 in the moduli, so sum_c E_c dC/dE_c = -C."""
     prob, phi = _problems()[case]
@@ -45,7 +46,7 @@ def test_uniform_bar_sensitivity():
     np.testing.assert_allclose(g[0], -prob.p * C / prob.ncell, rtol=1e-12)
 
 
-@pytest.mark.parametrize("case", range(4))
+@pytest.mark.parametrize("case", range(5))
 def test_finite_differences(case):
     prob, phi = _problems()[case]
     u, C = _direct(phi, prob)

@@ -152,6 +152,31 @@ def multimaterial3d(nx=256, ny=128, nz=128, e_phase=(1.0, 0.5, 1e-9), nu=0.3, p=
                    name=f"multimaterial3d_{nx}x{ny}x{nz}")
 
 
+def mbb2d(nx=512, ny=128, e_phase=(1.0, 0.775, 0.55, 0.325, 0.1, 1e-6), nu=0.3, p=3.0,
+          vol_frac=(0.08,) * 5):
+    """The paper's 2D multi-material MBB beam (Section 3.2): a 4 x 1 domain, five
+    solid phases plus void (moduli and fractions as printed), a downward unit force
+    at the middle of the top side (split over the two top y-faces next to it),
+    rollers under both bottom corners (u_y of their bottom faces held).  Reading:
+    u_x of the bottom-left corner face is held too, removing the rigid x
+    translation the rollers leave free (its reaction is zero by symmetry)."""
+    side = (FREE,) * 6
+    n = (nx, ny)
+    fixed = np.zeros((2, ny + 1, nx + 1), dtype=np.uint8)
+    fixed[_idx(2, 1, 0, 0)] = 1
+    fixed[_idx(2, 1, nx - 1, 0)] = 1
+    fixed[_idx(2, 0, 0, 0)] = 1
+    load = np.zeros((2, ny + 1, nx + 1))
+    if nx % 2 == 0:
+        load[_idx(2, 1, nx // 2 - 1, ny)] = -0.5
+        load[_idx(2, 1, nx // 2, ny)] = -0.5
+    else:
+        load[_idx(2, 1, nx // 2, ny)] = -1.0
+    return Problem(ELASTIC, 2, n, 1.0 / ny, 1.0, 0.0, nu, p, side, fixed, load,
+                   nphase=len(e_phase) - 1, e_phase=tuple(e_phase), vol_frac=tuple(vol_frac),
+                   name=f"mbb2d_{nx}x{ny}")
+
+
 def uniform_bar(ndim, n, t=1.0, E=1.0, nu=0.3):
     """Bar under uniform axial traction: roller on x=0, symmetry-plane pins on the
     mid y-face row (and mid z-face layer in 3D), traction t on the x=end faces.
