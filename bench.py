@@ -55,8 +55,12 @@ def parse():
                     help="re-choose the damping at every check from the state's Rayleigh quotient")
     ap.add_argument("--schedule", default="tolerance", choices=["tolerance", "paper"],
                     help="paper: the paper's loop (n_APT damped-wave + n_PT plain PT sweeps, penalty update, "
-                         "one Cahn-Hilliard step) in FP32, on the 2D cantilever or (--workload "
-                         "paper_heat2d_512) the paper's 2D heat set-up")
+                         "one Cahn-Hilliard step) in FP32, on the 2D cantilever, the paper's 2D heat "
+                         "set-up (--workload paper_heat2d_512) or its five-material MBB beam "
+                         "(--workload mbb2d_512x128)")
+    ap.add_argument("--alpha-v", type=float, default=None,
+                    help="paper schedule: volume-penalty weight (default 1e5 as printed; for the MBB beam "
+                         "0.25 / (N h^2d), since 1e5 makes its volume mode unstable there)")
     ap.add_argument("--n-apt", type=int, default=20)
     ap.add_argument("--n-pt", type=int, default=20)
     ap.add_argument("--ttd-steps", type=int, default=0,
@@ -272,6 +276,10 @@ def paper_leg(args):
         n = int(args.workload.split("_")[-1]) if args.workload.split("_")[-1].isdigit() else 512
         prob = W.paper_heat2d(n)
         workload, family, bpc = prob.name, "heat", bytes_per_cell("heat")
+    elif args.workload.startswith("mbb2d"):
+        nx, ny = (int(x) for x in args.workload.split("_")[1].split("x"))
+        prob = W.mbb2d(nx, ny)
+        workload, family, bpc = prob.name, "el2d", BYTES_PER_CELL_2D_FP32
     else:
         prob = W.cantilever2d(args.nx, args.ny)
         workload, family, bpc = f"cantilever2d_{args.nx}x{args.ny}", "el2d", BYTES_PER_CELL_2D_FP32
@@ -283,7 +291,13 @@ def paper_leg(args):
     comp = torch.zeros(2, dtype=torch.float64, device="cuda")
     ce = args.n_apt if args.n_apt % 2 == 0 else 2
     apt = dict(theta=args.theta, replay_iters=args.n_apt, check_every=ce, n_pt=args.n_pt)
-    phase = dict(model="penalty")
+    # the volume mode of the penalty update moves the phase volume by a factor
+    # 1 - 2 alpha_v N h^(2d) per step: the printed 1e5 is stable for the paper's
+    # heat set-up (0.76) but not for the MBB beam (48.8)
+    hd = prob.h ** prob.ndim
+    alpha_v = args.alpha_v if args.alpha_v is not None else (
+        0.25 / (prob.ncell * hd * hd) if args.workload.startswith("mbb2d") else 1e5)
+    phase = dict(model="penalty", alpha_v=alpha_v)
 
     def step():
         ctx.step(phi, u, v, g, vol_frac=prob.vol_frac, compliance=comp, apt=apt, phase=phase)
@@ -303,8 +317,10 @@ def paper_leg(args):
            "warmup": args.warmup, "ms_per_step": 1000.0 * wall / args.steps, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": workload, "cells": prob.ncell, "n_apt": args.n_apt,
-                      "n_pt": args.n_pt, "theta": args.theta, "compliance": comp[0].item(),
-                      "mean_phi": float(phi.double().mean().item())}}
+                      "n_pt": args.n_pt, "theta": args.theta, "alpha_v": alpha_v,
+                      "volume_gain": 2.0 * alpha_v * prob.ncell * hd * hd, "compliance": comp[0].item(),
+                      "mean_phi": [float(x) for x in phi.double().view(prob.nphase, -1).mean(dim=1).tolist()],
+                      "finite": bool(torch.isfinite(phi).all().item())}}
     out["roofline"] = kernel_roofline(ctx, bpc * prob.ncell, family, workload)
     ctx.close()
     print(json.dumps(out))
