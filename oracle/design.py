@@ -16,7 +16,8 @@ infrastructure only).
   no-flux mirror boundaries), then the volume constraint enforced exactly by a
   uniform shift s found by bisection in FP64 (the role of the penalty J_v of
   Eq. (2.10)).  Several solid phases are projected one after another, each bounded
-  above by what the earlier phases leave.
+  above by what the earlier phases leave; cells of a void region are held at 0 and
+  passive-solid cells at 1 (phase 0) by the same bounds.
 * Design step (Fig. 4): relax the state, evaluate compliance and sensitivity,
   update the design.
 """
@@ -176,17 +177,32 @@ def volume(phi_shifted_clamped):
     return float(np.sum(phi_shifted_clamped))
 
 
-def bisect_shift(x, ub, target, iters=64):
-    """s with sum(clip(x + s, 0, ub)) = target, by bisection on [-max x, max(ub) - min x]."""
+def bisect_shift(x, ub, target, iters=64, lb=0.0):
+    """s with sum(clip(x + s, lb, ub)) = target, by bisection on [-max x, max(ub) - min x]."""
     lo = -float(np.max(x))
     hi = float(np.max(ub)) - float(np.min(x))
     for _ in range(iters):
         mid = 0.5 * (lo + hi)
-        if float(np.sum(np.clip(x + mid, 0.0, ub))) < target:
+        if float(np.sum(np.clip(x + mid, lb, ub))) < target:
             lo = mid
         else:
             hi = mid
     return 0.5 * (lo + hi)
+
+
+def region_bounds(prob, m, used):
+    """Per-cell bounds of phase m: void-region cells held at 0, passive-solid cells
+    hold phase 0 at 1 (later phases then have no room), design cells in
+    [0, 1 - used] (Section 3.4's void region as a hard constraint)."""
+    ub = 1.0 - used
+    lb = np.zeros_like(ub)
+    reg = prob.region
+    if reg is not None:
+        ub = np.where(reg == 1, 0.0, ub)
+        if m == 0:
+            lb = np.where(reg == 2, 1.0, lb)
+            ub = np.where(reg == 2, 1.0, ub)
+    return lb, ub
 
 
 @dataclass
@@ -210,9 +226,9 @@ def phase_update(phi, g, prob, params=PhaseParams()):
         ghat = g[m] / gmax if gmax > 0 else np.zeros_like(g[m])
         p1 = phi[m] - params.alpha_h * ghat
         p2 = p1 - dt_ac * (double_well_derivative(p1) - params.gamma * laplacian_mirror(p1, h))
-        ub = 1.0 - used
-        s = bisect_shift(p2, ub, vf[m] * N, params.bisect_iters)
-        out[m] = np.clip(p2 + s, 0.0, ub)
+        lb, ub = region_bounds(prob, m, used)
+        s = bisect_shift(p2, ub, vf[m] * N, params.bisect_iters, lb)
+        out[m] = np.clip(p2 + s, lb, ub)
         used = used + out[m]
         info.shift.append(s)
         info.volume.append(float(np.mean(out[m])))

@@ -12,7 +12,11 @@ Besides the solve-to-tolerance / Allen-Cahn / exact-projection loop of
   partition-of-unity penalty J_1 = int (sum_i phi_i - 1)^2 dOmega (Eq. (2.11));
 * one explicit Cahn-Hilliard step (Eq. (2.14), forward Euler in time, finite
   differences in space, Section 2.4): mu = w'(phi) - gamma Lap(phi),
-  phi <- phi + dt3 D Lap(mu), no-flux (mirror) boundaries for both fields.
+  phi <- phi + dt3 D Lap(mu), no-flux (mirror) boundaries for both fields;
+* the void-region penalty of the drone example (Section 3.4):
+  alpha_b dJ_b/dphi with J_b = (int_{Omega_b} phi dOmega - V^b)^2, V^b = 0 for a
+  solid phase (the void phase, V^b = 1, is implicit here); passive-solid cells are
+  reset to phase 0 after the step.
 
 Readings (the paper leaves them open): the integral is the cell sum times h^d; the
 target V_i of J_v is the volume V_f,i |Omega| (the printed form compares an
@@ -37,6 +41,8 @@ class PenaltyParams:
     alpha_v: float = 1e5          # volume-penalty weight
     alpha_1: float = 0.0          # partition-of-unity weight (1e4 in the paper, whose
                                   # void phase is a stored field)
+    alpha_b: float = 0.0          # void-region weight (the drone example, Section 3.4;
+                                  # the region is the problem's REGION_VOID cells)
     gamma: float = 3e-5           # interface parameter of Eq. (2.14)
     mobility: float = 1.0         # D of Eq. (2.14)
     dt_ch: float | None = None    # None: 500 h^4
@@ -60,6 +66,14 @@ def partition_penalty_gradient(phi, h, ndim):
     return 2.0 * (np.sum(phi, axis=0) - 1.0) * h ** ndim
 
 
+def void_region_gradient(phi_m, region, h, ndim):
+    """dJ_b/dphi_c of one solid phase, J_b = (int_{Omega_b} phi dOmega - 0)^2:
+    2 (h^d sum_{Omega_b} phi) h^d on the region's cells, 0 elsewhere."""
+    hd = h ** ndim
+    inb = region == 1
+    return np.where(inb, 2.0 * (hd * float(np.sum(phi_m[inb]))) * hd, 0.0)
+
+
 def cahn_hilliard_step(p, h, gamma, mobility, dt):
     """phi + dt D Lap(w'(phi) - gamma Lap(phi)), mirror boundaries."""
     mu = design.double_well_derivative(p) - gamma * design.laplacian_mirror(p, h)
@@ -81,7 +95,12 @@ def penalty_update(phi, g, prob, params=PenaltyParams()):
         ghat = g[m] / gmax if gmax > 0 else np.zeros_like(g[m])
         vpen = params.alpha_v * volume_penalty_gradient(phi[m], vf[m], h, nd)
         p1 = phi[m] - params.alpha_h * ghat - vpen - params.alpha_1 * pgrad
+        if params.alpha_b != 0.0 and prob.region is not None:
+            p1 = p1 - params.alpha_b * void_region_gradient(phi[m], prob.region, h, nd)
         out[m] = cahn_hilliard_step(p1, h, params.gamma, params.mobility, dt)
+        if prob.region is not None:
+            # passive-solid cells: phase 0 held at 1, the others at 0
+            out[m] = np.where(prob.region == 2, 1.0 if m == 0 else 0.0, out[m])
         info.shift.append(-vpen)
         info.volume.append(float(np.mean(out[m])))
         info.gmax.append(gmax)

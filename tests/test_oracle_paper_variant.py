@@ -144,3 +144,53 @@ def test_material_laws_clamp_the_fractions():
     assert d[0, 0, 0] == 0.0 and d[0, 0, 2] == 0.0 and d[0, 1, 3] == 0.0 and d[0, 0, 1] > 0.0
     probs, phis, _ = W.heat_batch(1, 6, 6, seed=1)
     assert heat.conductivity(phi, probs[0]).min() >= probs[0].emin
+
+
+def _region_problem():
+    prob = W.cantilever2d(16, 8)
+    reg = np.zeros((8, 16), dtype=np.uint8)
+    reg[2:6, 6:10] = W.REGION_VOID
+    reg[:, 0] = W.REGION_SOLID
+    prob.region = reg
+    return prob
+
+
+def test_void_region_gradient_against_finite_differences():
+    prob = _region_problem()
+    rng = np.random.default_rng(3)
+    phi = rng.uniform(0, 1, (8, 16))
+    h, nd = prob.h, 2
+    jb = lambda p: (h ** nd * np.sum(p[prob.region == 1])) ** 2
+    gb = pv.void_region_gradient(phi, prob.region, h, nd)
+    d = 1e-4
+    for c in [(3, 7), (0, 3), (5, 9)]:
+        pp, pm = phi.copy(), phi.copy()
+        pp[c] += d
+        pm[c] -= d
+        assert gb[c] == pytest.approx((jb(pp) - jb(pm)) / (2 * d), rel=1e-8, abs=1e-20)
+
+
+def test_regions_in_the_allen_cahn_update():
+    """Void-region cells end at 0, passive-solid cells at 1, the volume is exact."""
+    prob = _region_problem()
+    rng = np.random.default_rng(4)
+    phi = rng.uniform(0, 1, (1, 8, 16))
+    g = -rng.random(phi.shape)
+    out, info = design.phase_update(phi, g, prob)
+    assert np.all(out[0][prob.region == 1] == 0.0)
+    assert np.all(out[0][prob.region == 2] == 1.0)
+    assert np.mean(out[0]) == pytest.approx(prob.vol_frac[0], abs=1e-12)
+    assert out.min() >= 0.0 and out.max() <= 1.0
+
+
+def test_regions_in_the_penalty_update():
+    """The void-region term lowers the region's material; passive-solid cells are
+    reset to 1."""
+    prob = _region_problem()
+    phi = np.full((1, 8, 16), 0.5)
+    g = np.zeros_like(phi)
+    a, _ = pv.penalty_update(phi, g, prob, pv.PenaltyParams(alpha_b=0.0))
+    b, _ = pv.penalty_update(phi, g, prob, pv.PenaltyParams(alpha_b=1e5))
+    assert np.all(b[0][prob.region == 2] == 1.0)
+    inb = prob.region == 1
+    assert np.sum(b[0][inb]) < np.sum(a[0][inb])

@@ -28,6 +28,7 @@ import numpy as np
 
 FREE, CLAMPED, ROLLER = 0, 1, 2
 ELASTIC, HEAT = 0, 1
+REGION_DESIGN, REGION_VOID, REGION_SOLID = 0, 1, 2   # cell roles (passive regions)
 
 
 @dataclass
@@ -49,6 +50,7 @@ class Problem:
     e_phase: tuple = ()               # moduli of the solid phases, then the void
     vol_frac: tuple = (0.5,)
     name: str = ""
+    region: np.ndarray | None = None  # uint8 per cell: 0 design, REGION_VOID, REGION_SOLID
 
     @property
     def ncell(self) -> int:
@@ -175,6 +177,36 @@ def mbb2d(nx=512, ny=128, e_phase=(1.0, 0.775, 0.55, 0.325, 0.1, 1e-6), nu=0.3, 
     return Problem(ELASTIC, 2, n, 1.0 / ny, 1.0, 0.0, nu, p, side, fixed, load,
                    nphase=len(e_phase) - 1, e_phase=tuple(e_phase), vol_frac=tuple(vol_frac),
                    name=f"mbb2d_{nx}x{ny}")
+
+
+def drone3d(nx=128, ny=64, nz=128, vol_frac=0.15, void_box=((0.25, 0.75), (0.2, 1.0), (0.25, 0.75)),
+            nu=0.3, p=3.0):
+    """A synthetic stand-in for the paper's drone skeleton (Section 3.4; the
+    geometry of the cited source is not given): a 1 x 0.5 x 1 block (y up), u_y of
+    the top faces of the four top corner cells held (the printed rollers), a unit
+    downward load on the bottom face of the middle cell, and a void region Omega_b
+    (the battery bay) given as a box in units of the sides (default: 20 % of the
+    volume).  Reading: u_x and u_z of one top corner face and u_z of a second one
+    are held too, removing the rigid motions the rollers leave free."""
+    side = (FREE,) * 6
+    n = (nx, ny, nz)
+    fixed = np.zeros((3, nz + 1, ny + 1, nx + 1), dtype=np.uint8)
+    corners = ((0, 0), (nx - 1, 0), (0, nz - 1), (nx - 1, nz - 1))
+    for (ci, ck) in corners:
+        fixed[_idx(3, 1, ci, ny, ck)] = 1
+    fixed[_idx(3, 0, 0, ny - 1, 0)] = 1
+    fixed[_idx(3, 2, 0, ny - 1, 0)] = 1
+    fixed[_idx(3, 2, nx - 1, ny - 1, 0)] = 1
+    load = np.zeros((3, nz + 1, ny + 1, nx + 1))
+    load[_idx(3, 1, nx // 2, 0, nz // 2)] = -1.0
+    region = np.zeros((nz, ny, nx), dtype=np.uint8)
+    (x0, x1), (y0, y1), (z0, z1) = void_box
+    xs = slice(int(round(x0 * nx)), int(round(x1 * nx)))
+    ys = slice(int(round(y0 * ny)), int(round(y1 * ny)))
+    zs = slice(int(round(z0 * nz)), int(round(z1 * nz)))
+    region[zs, ys, xs] = REGION_VOID
+    return Problem(ELASTIC, 3, n, 1.0 / nx, 1.0, 1e-6, nu, p, side, fixed, load,
+                   vol_frac=(vol_frac,), name=f"drone3d_{nx}x{ny}x{nz}", region=region)
 
 
 def uniform_bar(ndim, n, t=1.0, E=1.0, nu=0.3):
