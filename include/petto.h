@@ -59,6 +59,10 @@ enum { PETTO_ELASTIC = 0, PETTO_HEAT = 1 };
 enum { PETTO_FP32 = 0, PETTO_FP64 = 1 };
 enum { PETTO_SIDE_FREE = 0, PETTO_SIDE_CLAMPED = 1, PETTO_SIDE_ROLLER = 2 };
 enum { PETTO_FIELD_STATE = 0, PETTO_FIELD_CELL = 1 };
+/* Cell roles.  VOID: every solid phase held at 0 by the Allen-Cahn update's bounds,
+ * and the J_b penalty of the penalty model (weight alpha_b).  SOLID: phase 0 held
+ * at 1 (the other phases at 0) after either update. */
+enum { PETTO_REGION_DESIGN = 0, PETTO_REGION_VOID = 1, PETTO_REGION_SOLID = 2 };
 
 #define PETTO_MAX_PHASES 6
 
@@ -90,6 +94,8 @@ typedef struct {
   const uint8_t *fixed;
   const double *load;
   double q;
+  const uint8_t *region;    /* host, one byte per cell ([nz][ny][nx]) or NULL: PETTO_REGION_*
+                               (the void region of Section 3.4 and passive solid cells) */
 } petto_problem;
 
 /* Pseudo-transient relaxation controls (Section 2.2, Eqs. 2.5-2.6 / 3.12).
@@ -156,6 +162,7 @@ typedef struct {
   double alpha_1;           /* penalty model: partition-of-unity weight (0 with an implicit void) */
   double dt_ch;             /* penalty model: Cahn-Hilliard step; <= 0: 500 h^4 */
   double mobility;          /* penalty model: D of Eq. 2.14; <= 0: 1 */
+  double alpha_b;           /* penalty model: void-region weight, J_b = (int_{Omega_b} phi - 0)^2 */
 } petto_phase_params;
 
 typedef struct {

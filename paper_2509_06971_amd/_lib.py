@@ -29,6 +29,7 @@ class Problem(C.Structure):
         ("e0", C.c_double), ("emin", C.c_double), ("nu", C.c_double), ("p", C.c_double),
         ("nphase", C.c_int32), ("e_phase", C.c_double * (MAX_PHASES + 1)), ("side", C.c_int32 * 6),
         ("fixed", C.POINTER(C.c_uint8)), ("load", C.POINTER(C.c_double)), ("q", C.c_double),
+        ("region", C.POINTER(C.c_uint8)),
     ]
 
 
@@ -45,6 +46,7 @@ class PhaseParams(C.Structure):
         ("alpha_h", C.c_double), ("gamma", C.c_double), ("dt_ac", C.c_double),
         ("vol_frac", C.c_double * MAX_PHASES), ("bisect_passes", C.c_int32), ("model", C.c_int32),
         ("alpha_v", C.c_double), ("alpha_1", C.c_double), ("dt_ch", C.c_double), ("mobility", C.c_double),
+        ("alpha_b", C.c_double),
     ]
 
 

@@ -35,6 +35,10 @@ def _problem_struct(p, keep):
         keep.append(ld)
         s.load = ld.ctypes.data_as(C.POINTER(C.c_double))
     s.q = float(getattr(p, "q", 0.0))
+    if getattr(p, "region", None) is not None:
+        rg = np.ascontiguousarray(p.region, dtype=np.uint8)
+        keep.append(rg)
+        s.region = rg.ctypes.data_as(C.POINTER(C.c_uint8))
     return s
 
 
@@ -104,7 +108,7 @@ class Context:
 
     @staticmethod
     def phase_params(vol_frac, alpha_h=0.1, gamma=3e-5, dt_ac=0.0, bisect_passes=0, model="allen_cahn",
-                     alpha_v=1e5, alpha_1=0.0, dt_ch=0.0, mobility=1.0):
+                     alpha_v=1e5, alpha_1=0.0, dt_ch=0.0, mobility=1.0, alpha_b=0.0):
         """model: "allen_cahn" (Allen-Cahn step + exact volume projection) or
         "penalty" (the paper's penalty update + one Cahn-Hilliard step)."""
         p = L.PhaseParams()
@@ -115,6 +119,7 @@ class Context:
         p.bisect_passes = int(bisect_passes)
         p.model = {"allen_cahn": 0, "penalty": 1}[model]
         p.alpha_v, p.alpha_1, p.dt_ch, p.mobility = float(alpha_v), float(alpha_1), float(dt_ch), float(mobility)
+        p.alpha_b = float(alpha_b)
         return p
 
     # ------------------------------------------------------------------ entry points

@@ -203,6 +203,7 @@ struct PhaseArgs {
   double* work;             // phi'' of this design (double)
   double* partial;          // per block scratch, >= nblocks * 64
   double* scal;             // [0] gmax [1] lo [2] hi [3] s [4] mean phi [5] target sum
+                            // [6] sum phi [7] sum phi over the void region
   int nx, ny, nz;           // cells (nz = 1 in 2D)
   int ndim;
   long n;
@@ -212,6 +213,10 @@ struct PhaseArgs {
   const double* total;      // sum of all stored phases of the old design, or nullptr (this phase alone)
   double* work2;            // chemical potential mu (double)
   double alpha_v, alpha_1, vol_frac, dt_ch, mobility;
+  // regions (nullptr: every cell is a design cell)
+  const uint8_t* region;    // PETTO_REGION_* per cell of this design
+  int first;                // this is phase 0 (passive-solid cells hold it at 1)
+  double alpha_b;           // penalty model: void-region weight
 };
 template <typename T> void launch_phase_gmax(const PhaseArgs<T>& a, hipStream_t s);
 template <typename T> void launch_phase_step(const PhaseArgs<T>& a, hipStream_t s);

@@ -79,6 +79,7 @@ struct petto_ctx {
   HeatDesign* d_des = nullptr;
   HeatTile* d_tiles = nullptr;
   uint8_t* d_dir = nullptr;
+  uint8_t* d_region = nullptr;         // PETTO_REGION_* per cell, or nullptr
   int* d_tile0 = nullptr;
   int ntile = 0;                       // partial-sum slots (largest tiling)
   std::map<int, TileList> heat_lists;  // heat work lists per sweeps-per-launch
@@ -184,6 +185,12 @@ petto_status validate_problem(const petto_problem& p, int idx) {
       return fail(PETTO_ERR_INVALID, "problem %d: n[%d]=%d outside [2, 65536]", idx, a, p.n[a]);
   }
   if (!(p.h > 0.0) || !is_finite(p.h)) return fail(PETTO_ERR_INVALID, "problem %d: h must be positive", idx);
+  if (p.region != nullptr) {
+    long n = (long)p.n[0] * p.n[1] * (p.ndim == 3 ? p.n[2] : 1);
+    for (long q = 0; q < n; ++q)
+      if (p.region[q] > PETTO_REGION_SOLID)
+        return fail(PETTO_ERR_INVALID, "problem %d: region[%ld] = %d is not a cell role", idx, q, (int)p.region[q]);
+  }
   if (p.nphase < 1 || p.nphase > kMaxPhase)
     return fail(PETTO_ERR_INVALID, "problem %d: nphase must be in [1, %d]", idx, kMaxPhase);
   if (!(p.p >= 1.0) || !is_finite(p.p)) return fail(PETTO_ERR_INVALID, "problem %d: penalty p must be >= 1", idx);
@@ -875,6 +882,9 @@ petto_status phase_update_impl(petto_ctx* c, void* phi, const void* grad, const 
         a.vol_frac = pp->vol_frac[m];
         a.dt_ch = pp->dt_ch > 0.0 ? pp->dt_ch : 500.0 * h * h * h * h;
         a.mobility = pp->mobility > 0.0 ? pp->mobility : 1.0;
+        a.region = c->d_region != nullptr ? c->d_region + R.off : nullptr;
+        a.first = m == 0;
+        a.alpha_b = pp->alpha_b;
         a.nblocks = phase_blocks(R.n);
       }
       // every phase's step from the old design, then the Cahn-Hilliard steps
@@ -916,6 +926,8 @@ petto_status phase_update_impl(petto_ctx* c, void* phi, const void* grad, const 
       a.gamma = pp->gamma;
       a.dt_ac = dt_ac;
       a.target = pp->vol_frac[m] * (double)R.n;
+      a.region = c->d_region != nullptr ? c->d_region + R.off : nullptr;
+      a.first = m == 0;
       a.nblocks = phase_blocks(R.n);
       launch_phase_gmax<T>(a, s);
       launch_phase_step<T>(a, s);
@@ -1138,6 +1150,16 @@ petto_status petto_create(const petto_problem* probs, int32_t nprob, int32_t pre
       hh.push_back(r.h);
     }
     PETTO_TRY(upload(c, &c->d_ranges, c->h_ranges));
+    // cell roles, concatenated like the cell arrays (only when a design has them)
+    bool any_region = false;
+    for (int d = 0; d < nprob; ++d) any_region = any_region || probs[d].region != nullptr;
+    if (any_region) {
+      std::vector<uint8_t> reg((size_t)c->ncell, 0);
+      for (int d = 0; d < nprob; ++d)
+        if (probs[d].region != nullptr)
+          std::copy(probs[d].region, probs[d].region + c->h_ranges[d].n, reg.begin() + c->h_ranges[d].off);
+      PETTO_TRY(upload(c, &c->d_region, reg));
+    }
     PETTO_TRY(upload(c, &c->d_ncell, nc));
     PETTO_TRY(upload(c, &c->d_fnorm, c->fnorm));
     PETTO_TRY(upload(c, &c->d_h, hh));
@@ -1413,6 +1435,7 @@ petto_status petto_phase_update(petto_ctx* ctx, void* phi, const void* grad_phi,
       return fail(PETTO_ERR_INVALID, "alpha_v and alpha_1 must be finite and >= 0");
     if (!is_finite(pp->dt_ch) || !is_finite(pp->mobility))
       return fail(PETTO_ERR_INVALID, "dt_ch and mobility must be finite (<= 0 selects the default)");
+    if (!(pp->alpha_b >= 0.0) || !is_finite(pp->alpha_b)) return fail(PETTO_ERR_INVALID, "alpha_b must be >= 0");
   }
   double vs = 0.0;
   for (int m = 0; m < ctx->nphase; ++m) {

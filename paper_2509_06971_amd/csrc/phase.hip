@@ -34,6 +34,24 @@ __global__ void gmax_final_kernel(const double* partial, int nb, double* scal) {
   if (threadIdx.x == 0) scal[0] = m;
 }
 
+// Bounds of a cell for this phase: design cells [0, 1 - used]; void-region cells
+// held at 0; passive-solid cells hold phase 0 at 1 (the later phases then find
+// no room, since `used` already counts it).
+template <typename T>
+__device__ inline void cell_bounds(const PhaseArgs<T>& A, long c, double& lb, double& ub) {
+  ub = A.used == nullptr ? 1.0 : 1.0 - A.used[c];
+  lb = 0.0;
+  if (A.region != nullptr) {
+    const uint8_t r = A.region[c];
+    if (r == 1) {
+      ub = 0.0;
+    } else if (r == 2 && A.first) {
+      lb = 1.0;
+      ub = 1.0;
+    }
+  }
+}
+
 template <typename T>
 __device__ inline double sens_step(const PhaseArgs<T>& A, long c, double gmax) {
   const double gh = gmax > 0.0 ? (double)A.g[c] / gmax : 0.0;
@@ -46,7 +64,7 @@ __global__ __launch_bounds__(kBlock) void step_kernel(PhaseArgs<T> A) {
   const double gmax = A.scal[0];
   const double rh2 = 1.0 / (A.h * A.h);
   const double kPi = 3.141592653589793;
-  double mn = INFINITY, mx = -INFINITY, ubmax = (A.used == nullptr) ? 1.0 : -INFINITY;
+  double mn = INFINITY, mx = -INFINITY, ubmax = -INFINITY;
   const long sxy = (long)A.nx * A.ny;
   for (long c = (long)blockIdx.x * kBlock + threadIdx.x; c < A.n; c += (long)gridDim.x * kBlock) {
     const int k = (int)(c / sxy);
@@ -70,7 +88,9 @@ __global__ __launch_bounds__(kBlock) void step_kernel(PhaseArgs<T> A) {
     A.work[c] = y;
     mn = fmin(mn, y);
     mx = fmax(mx, y);
-    if (A.used != nullptr) ubmax = fmax(ubmax, 1.0 - A.used[c]);
+    double lb, ub;
+    cell_bounds(A, c, lb, ub);
+    ubmax = fmax(ubmax, ub);
   }
   const double a = block_min(mn, red);
   const double b = block_max(mx, red);
@@ -110,9 +130,10 @@ __global__ __launch_bounds__(kBlock) void pass_kernel(PhaseArgs<T> A) {
   for (int k = 0; k < kCand; ++k) acc[k] = 0.0;
   for (long c = (long)blockIdx.x * kBlock + threadIdx.x; c < A.n; c += (long)gridDim.x * kBlock) {
     const double x = A.work[c];
-    const double ub = A.used == nullptr ? 1.0 : 1.0 - A.used[c];
+    double lb, ub;
+    cell_bounds(A, c, lb, ub);
 #pragma unroll
-    for (int k = 0; k < kCand; ++k) acc[k] += fmin(fmax(x + (lo + (k + 1) * step), 0.0), ub);
+    for (int k = 0; k < kCand; ++k) acc[k] += fmin(fmax(x + (lo + (k + 1) * step), lb), ub);
   }
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
 #pragma unroll
@@ -159,8 +180,9 @@ __global__ __launch_bounds__(kBlock) void apply_kernel(PhaseArgs<T> A) {
   const double s = 0.5 * (A.scal[1] + A.scal[2]);
   double acc = 0.0;
   for (long c = (long)blockIdx.x * kBlock + threadIdx.x; c < A.n; c += (long)gridDim.x * kBlock) {
-    const double ub = A.used == nullptr ? 1.0 : 1.0 - A.used[c];
-    const T y = (T)fmin(fmax(A.work[c] + s, 0.0), ub);
+    double lb, ub;
+    cell_bounds(A, c, lb, ub);
+    const T y = (T)fmin(fmax(A.work[c] + s, lb), ub);
     A.phi[c] = y;
     acc += (double)y;
     if (A.used_out != nullptr) A.used_out[c] = (A.used == nullptr ? 0.0 : A.used[c]) + (double)y;
@@ -190,11 +212,22 @@ __global__ __launch_bounds__(kBlock) void sum_kernel(PhaseArgs<T> A) {
   if (threadIdx.x == 0) A.partial[blockIdx.x] = t;
 }
 
-__global__ void sum_final_kernel(const double* partial, int nb, double* scal) {
+__global__ void sum_final_kernel(const double* partial, int nb, double* scal, int slot) {
   double s = 0.0;
   for (int b = threadIdx.x; b < nb; b += kWave) s += partial[b];
   s = wave_sum(s);
-  if (threadIdx.x == 0) scal[6] = s;
+  if (threadIdx.x == 0) scal[slot] = s;
+}
+
+// sum of the phase over the void region
+template <typename T>
+__global__ __launch_bounds__(kBlock) void region_sum_kernel(PhaseArgs<T> A) {
+  __shared__ double red[kBlock / kWave];
+  double acc = 0.0;
+  for (long c = (long)blockIdx.x * kBlock + threadIdx.x; c < A.n; c += (long)gridDim.x * kBlock)
+    acc += A.region[c] == 1 ? (double)A.phi[c] : 0.0;
+  const double t = block_sum(acc, red);
+  if (threadIdx.x == 0) A.partial[blockIdx.x] = t;
 }
 
 // phi' = phi - alpha_h g / max|g| - alpha_v dJ_v/dphi - alpha_1 dJ_1/dphi (every
@@ -213,6 +246,7 @@ __global__ __launch_bounds__(kBlock) void penalty_kernel(PhaseArgs<T> A) {
       const double tot = A.total != nullptr ? A.total[c] : f;
       y = y - A.alpha_1 * (2.0 * (tot - 1.0) * hd);
     }
+    if (A.alpha_b != 0.0 && A.region != nullptr && A.region[c] == 1) y = y - A.alpha_b * (2.0 * (hd * A.scal[7]) * hd);
     A.work[c] = y;
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) A.scal[3] = -vpen;
@@ -263,7 +297,8 @@ __global__ __launch_bounds__(kBlock) void ch_kernel(PhaseArgs<T> A) {
     const int k = (int)(c / sxy);
     const long rem = c - (long)k * sxy;
     const int j = (int)(rem / A.nx), i = (int)(rem - (long)j * A.nx);
-    const double y = A.work[c] + step * lap_mirror(A.work2, c, i, j, k, A.nx, A.ny, A.nz, A.ndim, sxy, rh2);
+    double y = A.work[c] + step * lap_mirror(A.work2, c, i, j, k, A.nx, A.ny, A.nz, A.ndim, sxy, rh2);
+    if (A.region != nullptr && A.region[c] == 2) y = A.first ? 1.0 : 0.0;   // passive solid
     const T t = (T)y;
     A.phi[c] = t;
     acc += (double)t;
@@ -325,7 +360,11 @@ template <typename T>
 void launch_penalty_prep(const PhaseArgs<T>& a, hipStream_t s) {
   launch_phase_gmax<T>(a, s);
   hipLaunchKernelGGL((sum_kernel<T>), dim3(a.nblocks), dim3(kBlock), 0, s, a);
-  hipLaunchKernelGGL(sum_final_kernel, dim3(1), dim3(kWave), 0, s, a.partial, a.nblocks, a.scal);
+  hipLaunchKernelGGL(sum_final_kernel, dim3(1), dim3(kWave), 0, s, a.partial, a.nblocks, a.scal, 6);
+  if (a.alpha_b != 0.0 && a.region != nullptr) {
+    hipLaunchKernelGGL((region_sum_kernel<T>), dim3(a.nblocks), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(sum_final_kernel, dim3(1), dim3(kWave), 0, s, a.partial, a.nblocks, a.scal, 7);
+  }
 }
 
 template <typename T>
