@@ -276,6 +276,10 @@ def paper_leg(args):
         n = int(args.workload.split("_")[-1]) if args.workload.split("_")[-1].isdigit() else 512
         prob = W.paper_heat2d(n)
         workload, family, bpc = prob.name, "heat", bytes_per_cell("heat")
+    elif args.workload.startswith("drone3d"):
+        nx, ny, nz = (int(x) for x in args.workload.split("_")[1].split("x"))
+        prob = W.drone3d(nx, ny, nz)
+        workload, family, bpc = prob.name, "el3d", bytes_per_cell(prob.name)
     elif args.workload.startswith("mbb2d"):
         nx, ny = (int(x) for x in args.workload.split("_")[1].split("x"))
         prob = W.mbb2d(nx, ny)
@@ -296,8 +300,12 @@ def paper_leg(args):
     # heat set-up (0.76) but not for the MBB beam (48.8)
     hd = prob.h ** prob.ndim
     alpha_v = args.alpha_v if args.alpha_v is not None else (
-        0.25 / (prob.ncell * hd * hd) if args.workload.startswith("mbb2d") else 1e5)
+        0.25 / (prob.ncell * hd * hd) if args.workload.startswith(("mbb2d", "drone3d")) else 1e5)
     phase = dict(model="penalty", alpha_v=alpha_v)
+    if prob.region is not None:
+        # the void-region term with the same stability rule over the region's cells
+        nb = int(np.sum(prob.region == W.REGION_VOID))
+        phase["alpha_b"] = 0.25 / (nb * hd * hd)
 
     def step():
         ctx.step(phi, u, v, g, vol_frac=prob.vol_frac, compliance=comp, apt=apt, phase=phase)
@@ -320,7 +328,7 @@ def paper_leg(args):
                       "n_pt": args.n_pt, "theta": args.theta, "alpha_v": alpha_v,
                       "volume_gain": 2.0 * alpha_v * prob.ncell * hd * hd, "compliance": comp[0].item(),
                       "mean_phi": [float(x) for x in phi.double().view(prob.nphase, -1).mean(dim=1).tolist()],
-                      "finite": bool(torch.isfinite(phi).all().item())}}
+                      "finite": bool(torch.isfinite(phi).all().item()), "alpha_b": phase.get("alpha_b")}}
     out["roofline"] = kernel_roofline(ctx, bpc * prob.ncell, family, workload)
     ctx.close()
     print(json.dumps(out))

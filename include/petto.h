@@ -160,7 +160,9 @@ typedef struct {
   int32_t model;            /* PETTO_UPDATE_ALLEN_CAHN (above) or PETTO_UPDATE_PENALTY_CH */
   double alpha_v;           /* penalty model: volume-penalty weight (paper: 1e5) */
   double alpha_1;           /* penalty model: partition-of-unity weight (0 with an implicit void) */
-  double dt_ch;             /* penalty model: Cahn-Hilliard step; <= 0: 500 h^4 */
+  double dt_ch;             /* penalty model: Cahn-Hilliard step; <= 0: 500 h^4 capped at 0.9
+                               of the step's stability limit 2 / (D lam (pi^2/32 + gamma lam)),
+                               lam = 4 d / h^2 (the cap binds in 3D) */
   double mobility;          /* penalty model: D of Eq. 2.14; <= 0: 1 */
   double alpha_b;           /* penalty model: void-region weight, J_b = (int_{Omega_b} phi - 0)^2 */
 } petto_phase_params;

@@ -23,11 +23,12 @@ target V_i of J_v is the volume V_f,i |Omega| (the printed form compares an
 integral with a fraction, which agrees when |Omega| = 1); the gradient of every
 penalty is taken at the design before the step (one Jacobi step for all phases).
 The CH step uses the same mirror Laplacian as the Allen-Cahn step, so Lap(Lap) is
-the 13-point (2D) / 25-point (3D) biharmonic stencil.  Default dt3 = 500 h^4,
-D = 1.
+the 13-point (2D) / 25-point (3D) biharmonic stencil.  Default dt3 = 500 h^4
+capped at 0.9 of the step's stability limit (binding in 3D), D = 1.
 """
 from __future__ import annotations
 
+import math
 from dataclasses import dataclass
 
 import numpy as np
@@ -49,8 +50,15 @@ class PenaltyParams:
     vol_frac: tuple = ()          # default: the problem's
 
 
-def default_dt_ch(h):
-    return 500.0 * h ** 4
+def default_dt_ch(h, ndim=2, gamma=3e-5, mobility=1.0):
+    """The printed 500 h^4, capped at 0.9 of the explicit stability limit of the
+    step on the mirror Laplacian: a mode with Lap = -lam grows by
+    1 - dt D lam (w'' + gamma lam), so dt < 2 / (D lam (pi^2/32 + gamma lam)) for
+    the largest lam = 4 d / h^2.  (The printed step was set for the paper's wider
+    jnp.gradient stencil; with the compact stencil it exceeds the limit in 3D.)"""
+    lam = 4.0 * ndim / (h * h)
+    limit = 2.0 / (mobility * lam * (math.pi ** 2 / 32.0 + gamma * lam))
+    return min(500.0 * h ** 4, 0.9 * limit)
 
 
 def volume_penalty_gradient(phi_m, vf, h, ndim):
@@ -85,7 +93,7 @@ def penalty_update(phi, g, prob, params=PenaltyParams()):
     from the same old design.  Returns (phi_new, info) with info.shift the uniform
     volume-penalty term -alpha_v dJ_v/dphi of each phase."""
     h, nd = prob.h, prob.ndim
-    dt = params.dt_ch if params.dt_ch else default_dt_ch(h)
+    dt = params.dt_ch if params.dt_ch else default_dt_ch(h, nd, params.gamma, params.mobility)
     vf = params.vol_frac if params.vol_frac else prob.vol_frac
     pgrad = partition_penalty_gradient(phi, h, nd) if params.alpha_1 != 0.0 else 0.0
     out = np.empty_like(phi)

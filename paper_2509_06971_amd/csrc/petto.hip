@@ -880,8 +880,17 @@ petto_status phase_update_impl(petto_ctx* c, void* phi, const void* grad, const 
         a.alpha_v = pp->alpha_v;
         a.alpha_1 = pp->alpha_1;
         a.vol_frac = pp->vol_frac[m];
-        a.dt_ch = pp->dt_ch > 0.0 ? pp->dt_ch : 500.0 * h * h * h * h;
         a.mobility = pp->mobility > 0.0 ? pp->mobility : 1.0;
+        if (pp->dt_ch > 0.0) {
+          a.dt_ch = pp->dt_ch;
+        } else {
+          // the printed 500 h^4, capped at 0.9 of the explicit step's stability
+          // limit 2 / (D lam (pi^2/32 + gamma lam)), lam = 4 d / h^2
+          const double pi = 3.141592653589793;
+          const double lam = 4.0 * c->ndim / (h * h);
+          const double limit = 2.0 / (a.mobility * lam * (pi * pi / 32.0 + pp->gamma * lam));
+          a.dt_ch = std::fmin(500.0 * h * h * h * h, 0.9 * limit);
+        }
         a.region = c->d_region != nullptr ? c->d_region + R.off : nullptr;
         a.first = m == 0;
         a.alpha_b = pp->alpha_b;

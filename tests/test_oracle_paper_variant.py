@@ -33,6 +33,18 @@ def _eig(shape, modes, h):
 def test_default_ch_step_is_the_printed_value():
     h = GOLD["heat2d"]["dx"]
     assert pv.default_dt_ch(h) == pytest.approx(GOLD["heat2d"]["dt_ch_over_dx4"] * h ** 4)
+    # 3D on a coarser grid: the printed step is above the stability limit and is capped
+    assert pv.default_dt_ch(1 / 128, 3) < 500 * (1 / 128) ** 4
+
+
+@pytest.mark.parametrize("ndim,h", [(2, 1 / 512), (3, 1 / 128), (3, 1 / 64)])
+def test_default_ch_step_is_stable(ndim, h):
+    """The highest mirror-Laplacian mode (checkerboard, lam = 4 d / h^2) neither
+    grows nor flips sign unboundedly under the default step around a well."""
+    dt = pv.default_dt_ch(h, ndim)
+    lam = 4 * ndim / h ** 2
+    amp = 1 - dt * lam * (math.pi ** 2 / 32 + 3e-5 * lam)
+    assert abs(amp) < 1.0
     assert pv.PenaltyParams().alpha_v == GOLD["penalty"]["alpha_v"]
     assert pv.PenaltyParams().alpha_h == GOLD["penalty"]["alpha_h"]
 
