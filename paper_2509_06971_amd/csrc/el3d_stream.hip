@@ -30,9 +30,10 @@ constexpr int LX = TX + 3;   // halo column on each side, plus the x = nx face c
 template <typename T, int TY>
 struct Sm3 {
   static constexpr int LY = TY + 3;
+  T lead[LX];               // the first staged row's reads one row up land here (never used)
   T u[2][3][LY][LX];        // state planes (parity of the layer), with halo
   T e[2][LY][LX];           // cell moduli of the same layers
-  T sxx[LY][LX], syy[LY][LX];
+  T sxx[LY][LX], syy[LY][LX], szz[LY][LX];
   T txy[LY][LX];
   T txz[2][LY][LX];         // xz shear at z = layer (parity)
   T tyz[2][LY][LX];
@@ -63,19 +64,21 @@ __device__ __forceinline__ int reflect(int idx, int n, int clo, int chi, int& sr
   return 0;
 }
 
-// Entry flags (one bit each, kept in a vector register: per-lane booleans held as
-// scalar lane masks would exhaust the scalar registers).
-enum : unsigned {
-  kMe = 1u,        // the entry is a cell of the grid (modulus present)
-  kNrm = 2u,       // forms normal stresses (not the last row or column)
-  kShr = 4u,       // forms shear edges (not the first row or column)
-  kAxy = 8u,       // xy edge active (inside the z range)
-  kWxy = 16u,      // xy edge on a wall
-  kAxz = 32u,      // xz edge: xy part of the activity
-  kWxz = 64u,      // xz edge: on an x wall
-  kAyz = 128u,     // yz edge: xy part of the activity
-  kWyz = 256u,     // yz edge: on a y wall
-};
+// Element access at a byte offset from a workgroup-uniform base: the address is
+// a scalar base plus a 32-bit vector offset (no per-lane 64-bit arithmetic).
+// (The offset passes through an empty asm so that its zero extension is formed
+// beside the access, where instruction selection can fold it into the
+// scalar-base form, rather than hoisted out of the layer loop as a 64-bit value.)
+template <typename T>
+__device__ __forceinline__ T ldo(const T* __restrict__ base, unsigned off) {
+  asm volatile("" : "+v"(off));
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + off);
+}
+template <typename T>
+__device__ __forceinline__ void sto(T* __restrict__ base, unsigned off, T v) {
+  asm volatile("" : "+v"(off));
+  *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + off) = v;
+}
 
 // Bits of a thread's own-position word.
 enum : unsigned {
@@ -91,147 +94,161 @@ enum : unsigned {
   kXfok = 512u,    // ... where u_x exists
 };
 
-// What one staged LDS entry needs, worked out once per workgroup.
+// What one staged LDS entry needs, worked out once per workgroup.  The
+// multipliers are +1, -1 (reflected ghost of a clamped side) or 0; the edge
+// factors 0 (inactive), 1, or 2 (on a clamped wall), so that multiplying by
+// them is exact.
 template <typename T>
 struct Entry {
-  int ox, oy, oz, oe;       // in-layer source offsets (u_x, u_y, u_z, modulus)
-  T mx, my, mz;             // multipliers inside the z range: +1, -1 (reflected ghost) or 0
-  T gx, gy;                 // u_x / u_y multipliers on the z-ghost layers (0 at corners)
-  unsigned f;               // flags above
-  int eb, ea;               // LDS row and column
-  __device__ bool has(unsigned bit) const { return (f & bit) != 0u; }
+  unsigned ox, oy, oz, oe;  // in-layer byte offsets of the sources (u_x, u_y, u_z, modulus)
+  T mx, my, mz, me;         // multipliers on layers inside [0, nz)
+  T gx, gy;                 // u_x / u_y multipliers on a z-ghost layer (0 at corners)
+  T fxy, fxz, fyz;          // xy-position part of the xy, xz and yz edge factors
+  int q;                    // LDS index (row * LX + column)
 };
 
 template <typename T>
 __device__ __forceinline__ void make_entry(const ElGeom& g, int q, int i0, int j0, Entry<T>& E) {
   const int nx = g.nx, ny = g.ny;
-  E.eb = q / LX;
-  E.ea = q - E.eb * LX;
-  const int i = i0 - 1 + E.ea, j = j0 - 1 + E.eb;
+  const int eb = q / LX;
+  const int ea = q - eb * LX;
+  E.q = q;
+  const int i = i0 - 1 + ea, j = j0 - 1 + eb;
   int si, sj;
   bool gh_i, gh_j;
   const int ri = reflect(i, nx, g.clamp[0], g.clamp[1], si, gh_i);
   const int rj = reflect(j, ny, g.clamp[2], g.clamp[3], sj, gh_j);
+  constexpr unsigned W = sizeof(T);
   // u_x(i, j): own axis x in [0, nx], foreign axis y
   const bool own_x = i >= 0 && i <= nx;
   E.mx = T(own_x ? rj : 0);
-  E.ox = own_x ? sj * g.px + i : 0;
+  E.ox = (unsigned)(own_x ? sj * g.px + i : 0) * W;
   E.gx = gh_j ? T(0) : E.mx;
   // u_y(i, j): own axis y in [0, ny], foreign axis x
   const bool own_y = j >= 0 && j <= ny;
   E.my = T(own_y ? ri : 0);
-  E.oy = own_y ? j * g.px + si : 0;
+  E.oy = (unsigned)(own_y ? j * g.px + si : 0) * W;
   E.gy = gh_i ? T(0) : E.my;
   // u_z(i, j): foreign axes x and y; outside on both is a corner (zero)
   E.mz = T((gh_i && gh_j) ? 0 : ri * rj);
-  E.oz = sj * g.px + si;
+  E.oz = (unsigned)(sj * g.px + si) * W;
   // cell modulus
   const bool me = i >= 0 && i < nx && j >= 0 && j < ny;
-  E.oe = me ? j * nx + i : 0;
+  E.me = T(me ? 1 : 0);
+  E.oe = (unsigned)(me ? j * nx + i : 0) * W;
   bool on = false;
   const bool ai = edge_ok(i, nx, g.clamp[0], g.clamp[1], on);
   const bool aj = edge_ok(j, ny, g.clamp[2], g.clamp[3], on);
-  bool on2 = false;
-  const bool ai2 = edge_ok(i, nx, g.clamp[0], g.clamp[1], on2);
-  bool on3 = false;
-  const bool aj3 = edge_ok(j, ny, g.clamp[2], g.clamp[3], on3);
-  unsigned f = 0u;
-  f |= me ? kMe : 0u;
-  f |= (E.ea + 1 < LX) ? kNrm : 0u;
-  f |= (E.ea >= 1 && E.eb >= 1) ? kShr : 0u;
-  f |= (ai && aj) ? kAxy : 0u;
-  f |= on ? kWxy : 0u;
-  f |= (j >= 0 && j < ny && ai2) ? kAxz : 0u;
-  f |= on2 ? kWxz : 0u;
-  f |= (i >= 0 && i < nx && aj3) ? kAyz : 0u;
-  f |= on3 ? kWyz : 0u;
-  E.f = f;
-}
-
-template <typename T>
-__device__ __forceinline__ T apply_mult(T m, T v) {
-  return m == T(0) ? T(0) : m * v;
+  E.fxy = T((ai && aj) ? (on ? 2 : 1) : 0);
+  bool onx = false;
+  const bool axz = j >= 0 && j < ny && edge_ok(i, nx, g.clamp[0], g.clamp[1], onx);
+  E.fxz = T(axz ? (onx ? 2 : 1) : 0);
+  bool ony = false;
+  const bool ayz = i >= 0 && i < nx && edge_ok(j, ny, g.clamp[2], g.clamp[3], ony);
+  E.fyz = T(ayz ? (ony ? 2 : 1) : 0);
 }
 
 template <typename T, int TY>
 struct Plane {
   static constexpr int LY = TY + 3;
   static constexpr int NE = (LY * LX + TX * TY - 1) / (TX * TY);
-  T v[NE][4];   // u_x, u_y, u_z, modulus
+  T v[NE][4];   // u_x, u_y, u_z, modulus as loaded (multipliers applied when stored)
 };
 
-// Staging of z-layer k into registers.  Layer-uniform part: the source layers
-// and whether the layer is inside [0, nz), a z-ghost layer (k = -1 or nz: u_x,
-// u_y reflected across a clamped z side, else zero) or beyond (zero); u_z lives
-// on layers 0..nz and the modulus on 0..nz-1.
+// Whether the wave of this thread has staged entry e (uniform over the wave: a
+// wave past the staged count skips it; lanes of the boundary wave past the count
+// repeat the last entry).
+template <int TY>
+__device__ __forceinline__ bool wave_has_entry(int e) {
+  constexpr int LY = TY + 3;
+  if (e == 0) return true;
+  const int w0 = __builtin_amdgcn_readfirstlane((int)(threadIdx.x & ~(unsigned)(kWave - 1)));
+  return w0 + e * TX * TY < LY * LX;
+}
+
+// Issue the loads of z-layer k (source layers clamped into the arrays; what a
+// layer outside the grid holds is settled by the multipliers when stored).
 template <typename T, int TY>
 __device__ __forceinline__ void fetch_plane(const ElGeom& g, const T* __restrict__ ux, const T* __restrict__ uy,
-                                            const T* __restrict__ uz, const T* __restrict__ E, int S, int SE,
+                                            const T* __restrict__ uz, const T* __restrict__ E, long S, long SE,
                                             const Entry<T> (&en)[Plane<T, TY>::NE], int k, Plane<T, TY>& P) {
-  constexpr int LY = TY + 3;
   const int nz = g.nz;
   const int kxy = k < 0 ? 0 : (k >= nz ? nz - 1 : k);
   const int kzs = k < 0 ? 0 : (k > nz ? nz : k);
-  const bool inside = k >= 0 && k < nz;
-  const bool zghost = k == -1 || k == nz;
-  const T gs = T((k == -1 ? g.clamp[4] : g.clamp[5]) ? -1 : 0);
-  const bool zok = k >= 0 && k <= nz;
-  const int bxy = kxy * S, bz = kzs * S, be = kxy * SE;
+  const T* bx = ux + kxy * S;
+  const T* by = uy + kxy * S;
+  const T* bz = uz + kzs * S;
+  const T* be = E + kxy * SE;
 #pragma unroll
   for (int e = 0; e < Plane<T, TY>::NE; ++e) {
-    const int q = threadIdx.x + e * TX * TY;
-    if (e > 0 && q >= LY * LX) continue;
-    const T vx = ux[bxy + en[e].ox];
-    const T vy = uy[bxy + en[e].oy];
-    const T vz = uz[bz + en[e].oz];
-    const T ve = E != nullptr ? E[be + en[e].oe] : T(0);
-    const T fx = inside ? en[e].mx : (zghost ? gs * en[e].gx : T(0));
-    const T fy = inside ? en[e].my : (zghost ? gs * en[e].gy : T(0));
-    P.v[e][0] = apply_mult(fx, vx);
-    P.v[e][1] = apply_mult(fy, vy);
-    P.v[e][2] = zok ? apply_mult(en[e].mz, vz) : T(0);
-    P.v[e][3] = (inside && en[e].has(kMe)) ? ve : T(0);
+    if (!wave_has_entry<TY>(e)) continue;
+    P.v[e][0] = ldo(bx, en[e].ox);
+    P.v[e][1] = ldo(by, en[e].oy);
+    P.v[e][2] = ldo(bz, en[e].oz);
+    P.v[e][3] = ldo(be, en[e].oe);
   }
 }
 
+// Store z-layer k into LDS buffer buf.  Inside [0, nz) the xy multipliers
+// apply; a z-ghost layer (k = -1 or nz) holds u_x, u_y reflected across a
+// clamped z side (else zero); u_z lives on layers 0..nz and the modulus on
+// 0..nz-1; layers further out are zero.
 template <typename T, int TY>
-__device__ __forceinline__ void store_plane(const Plane<T, TY>& P, const Entry<T> (&en)[Plane<T, TY>::NE], int buf,
+__device__ __forceinline__ void store_plane(const ElGeom& g, const Plane<T, TY>& P,
+                                            const Entry<T> (&en)[Plane<T, TY>::NE], int k, int buf,
                                             Sm3<T, TY>& sm) {
-  constexpr int LY = TY + 3;
+  const int nz = g.nz;
+  T* U0 = &sm.u[buf][0][0][0];
+  T* U1 = &sm.u[buf][1][0][0];
+  T* U2 = &sm.u[buf][2][0][0];
+  T* EE = &sm.e[buf][0][0];
+  if (k >= 0 && k < nz) {
 #pragma unroll
-  for (int e = 0; e < Plane<T, TY>::NE; ++e) {
-    const int q = threadIdx.x + e * TX * TY;
-    if (e > 0 && q >= LY * LX) continue;
-    sm.u[buf][0][en[e].eb][en[e].ea] = P.v[e][0];
-    sm.u[buf][1][en[e].eb][en[e].ea] = P.v[e][1];
-    sm.u[buf][2][en[e].eb][en[e].ea] = P.v[e][2];
-    sm.e[buf][en[e].eb][en[e].ea] = P.v[e][3];
+    for (int e = 0; e < Plane<T, TY>::NE; ++e) {
+      if (!wave_has_entry<TY>(e)) continue;
+      const int q = en[e].q;
+      U0[q] = en[e].mx * P.v[e][0];
+      U1[q] = en[e].my * P.v[e][1];
+      U2[q] = en[e].mz * P.v[e][2];
+      EE[q] = en[e].me * P.v[e][3];
+    }
+  } else {
+    const T gs = T(((k == -1 && g.clamp[4]) || (k == nz && g.clamp[5])) ? -1 : 0);
+    const T sz = T(k >= 0 && k <= nz ? 1 : 0);
+#pragma unroll
+    for (int e = 0; e < Plane<T, TY>::NE; ++e) {
+      if (!wave_has_entry<TY>(e)) continue;
+      const int q = en[e].q;
+      U0[q] = (gs * en[e].gx) * P.v[e][0];
+      U1[q] = (gs * en[e].gy) * P.v[e][1];
+      U2[q] = (sz * en[e].mz) * P.v[e][2];
+      EE[q] = T(0);
+    }
   }
 }
 
-// xz / yz shear at z = kz of one entry from state planes lo (kz-1) and up (kz);
-// act_z / wall_z: the layer's part of the edge activity.
+// xz / yz shear at z = kz of one entry from state planes lo (kz-1) and up (kz)
+// into buffer dst.  c25 is mu0 / 4, or 0 when the z part of the edge is
+// inactive; s1 is 2 on a z wall, else 1 (the factor min(f s1, 2) then doubles
+// an edge on any wall).
 template <typename T, int TY>
-__device__ __forceinline__ void xz_yz_entry(const Entry<T>& E, int lo, int up, int dst, bool act_z, bool wall_z, T rh,
-                                            T mu0, Sm3<T, TY>& sm) {
-  const int b = E.eb, a = E.ea;
-  T txz = T(0), tyz = T(0);
-  if (E.has(kShr)) {
-    // xz edge (i, j+1/2, kz): cells (i-1..i, j, kz-1..kz)
-    const T m = el3d::edge_modulus<T>(mu0, sm.e[lo][b][a - 1], sm.e[lo][b][a], sm.e[up][b][a - 1], sm.e[up][b][a],
-                                      E.has(kAxz) && act_z, E.has(kWxz) || wall_z);
-    const T gam = el3d::shear_strain<T>(sm.u[up][0][b][a], sm.u[lo][0][b][a], sm.u[up][2][b][a],
-                                        sm.u[up][2][b][a - 1], rh);
-    txz = m * gam;
-    // yz edge (i+1/2, j, kz): cells (i, j-1..j, kz-1..kz)
-    const T m2 = el3d::edge_modulus<T>(mu0, sm.e[lo][b - 1][a], sm.e[lo][b][a], sm.e[up][b - 1][a], sm.e[up][b][a],
-                                       E.has(kAyz) && act_z, E.has(kWyz) || wall_z);
-    const T gam2 = el3d::shear_strain<T>(sm.u[up][1][b][a], sm.u[lo][1][b][a], sm.u[up][2][b][a],
-                                         sm.u[up][2][b - 1][a], rh);
-    tyz = m2 * gam2;
-  }
-  sm.txz[dst][b][a] = txz;
-  sm.tyz[dst][b][a] = tyz;
+__device__ __forceinline__ void xz_yz_entry(const Entry<T>& E, int lo, int up, int dst, T c25, T s1, T rh,
+                                            Sm3<T, TY>& sm) {
+  const int q = E.q;
+  const T* El = &sm.e[lo][0][0];
+  const T* Eu = &sm.e[up][0][0];
+  const T fxz = fmin(E.fxz * s1, T(2));
+  const T fyz = fmin(E.fyz * s1, T(2));
+  // xz edge (i, j+1/2, kz): cells (i-1..i, j, kz-1..kz)
+  const T m = (c25 * (((El[q - 1] + El[q]) + Eu[q - 1]) + Eu[q])) * fxz;
+  const T gam = el3d::shear_strain<T>((&sm.u[up][0][0][0])[q], (&sm.u[lo][0][0][0])[q], (&sm.u[up][2][0][0])[q],
+                                      (&sm.u[up][2][0][0])[q - 1], rh);
+  // yz edge (i+1/2, j, kz): cells (i, j-1..j, kz-1..kz)
+  const T m2 = (c25 * (((El[q - LX] + El[q]) + Eu[q - LX]) + Eu[q])) * fyz;
+  const T gam2 = el3d::shear_strain<T>((&sm.u[up][1][0][0])[q], (&sm.u[lo][1][0][0])[q], (&sm.u[up][2][0][0])[q],
+                                       (&sm.u[up][2][0][0])[q - LX], rh);
+  (&sm.txz[dst][0][0])[q] = m * gam;
+  (&sm.tyz[dst][0][0])[q] = m2 * gam2;
 }
 
 // sigma_zz of the own cell (i, j, k) from planes cur (k) and up (k+1)
@@ -246,30 +263,38 @@ __device__ __forceinline__ T own_szz(const Sm3<T, TY>& sm, int a, int b, int cur
   return szz;
 }
 
-// Result of one unknown at index gi: the damped update (sweep modes), the
-// residual (kResid) or its FP32 rounding (kRefine); r^2 summed on checking modes.
+// Result of one unknown: the damped update (sweep modes), the residual (kResid)
+// or its FP32 rounding (kRefine), written at byte offset off from the layer's
+// component bases; r^2 summed on checking modes.
 template <typename T, int MODE>
-__device__ __forceinline__ void finish(const ElSweep<T>& A, long gi, bool fix, T r, T un, T vn, T ca, T cc, T dt,
-                                       double& acc) {
+struct Out {
+  T* v;        // velocity (sweep modes) or residual (kResid)
+  T* u;        // state written (sweep modes)
+  float* r32;  // kRefine
+};
+
+template <typename T, int MODE>
+__device__ __forceinline__ void finish(const Out<T, MODE>& o, unsigned off, bool fix, T r, T un, T vn, T ca, T cc,
+                                       T dt, double& acc) {
   r = fix ? T(0) : r;
   if (MODE == kSweep || MODE == kCheck) {
     if (!fix) el3d::update<T>(ca, cc, dt, r, un, vn);
-    A.v[gi] = vn;
-    A.uout[gi] = un;
+    sto(o.v, off, vn);
+    sto(o.u, off, un);
   } else if (MODE == kResid) {
-    A.v[gi] = r;
+    sto(o.v, off, r);
   } else {
-    A.b32[gi] = (float)r;
+    sto(o.r32, off / (unsigned)(sizeof(T) / sizeof(float)), (float)r);
   }
   if (MODE == kCheck || MODE == kRefine) acc += (double)r * (double)r;
 }
 
 // Padding slot of a component array: written as zero.
 template <typename T, int MODE>
-__device__ __forceinline__ void zero_slot(const ElSweep<T>& A, long gi) {
-  if (MODE == kSweep || MODE == kCheck) A.uout[gi] = T(0);
-  else if (MODE == kResid) A.v[gi] = T(0);
-  else A.b32[gi] = 0.f;
+__device__ __forceinline__ void zero_slot(const Out<T, MODE>& o, unsigned off) {
+  if (MODE == kSweep || MODE == kCheck) sto(o.u, off, T(0));
+  else if (MODE == kResid) sto(o.v, off, T(0));
+  else sto(o.r32, off / (unsigned)(sizeof(T) / sizeof(float)), 0.f);
 }
 
 // Tiling: x-tiles of TX positions cover i < nx, and a tile ending at i = nx - 1
@@ -278,7 +303,7 @@ __device__ __forceinline__ void zero_slot(const ElSweep<T>& A, long gi) {
 // j = ny - 1 also takes the face row j = ny (only u_y) through its last wave;
 // z-tiles of KZ layers, the last one running through layer nz.
 template <typename T, int TY, int KZ, int MODE>
-__global__ __launch_bounds__(TX * TY) void el3d_stream_kernel(ElGeom g, ElSweep<T> A, int tiles_x, int tiles_y,
+__global__ __launch_bounds__(TX * TY, 4) void el3d_stream_kernel(ElGeom g, ElSweep<T> A, int tiles_x, int tiles_y,
                                                               int ntiles) {
   // the stop flag is read up front and tested after the first planes' loads are
   // issued, so the latencies overlap
@@ -287,6 +312,7 @@ __global__ __launch_bounds__(TX * TY) void el3d_stream_kernel(ElGeom g, ElSweep<
   constexpr int NE = Plane<T, TY>::NE;
   constexpr int LY = TY + 3;
   constexpr int XA = TX + 1;             // LDS column of the face column i = i0 + TX
+  constexpr unsigned W = sizeof(T);
   __shared__ Sm3<T, TY> sm;
   const int tile = xcd_tile(blockIdx.x, ntiles);
   const int txy = tiles_x * tiles_y;
@@ -300,13 +326,14 @@ __global__ __launch_bounds__(TX * TY) void el3d_stream_kernel(ElGeom g, ElSweep<
   const int i = i0 + lane, j = j0 + wave;
   const int nx = g.nx, ny = g.ny, nz = g.nz;
   const long pl = g.plane;
-  const int S = g.px * g.py;             // one layer of a component array
-  const int SE = nx * ny;                // one layer of the cell arrays
+  const long S = (long)g.px * g.py;      // one layer of a component array
+  const long SE = (long)nx * ny;         // one layer of the cell arrays
   const T* ux = A.uin;
   const T* uy = A.uin + pl;
   const T* uz = A.uin + 2 * pl;
   const T rh = T(1.0 / g.h), h2 = T(g.h * g.h);
   const T lam0 = T(g.lam0), mu0 = T(g.mu0);
+  const T c25 = T(0.25) * mu0;
   T ca = T(0), cc = T(0), dt = T(0);
   if (MODE == kSweep || MODE == kCheck) {
     ca = T(A.st->a);
@@ -316,20 +343,24 @@ __global__ __launch_bounds__(TX * TY) void el3d_stream_kernel(ElGeom g, ElSweep<
   Entry<T> en[NE];
 #pragma unroll
   for (int e = 0; e < NE; ++e) {
-    const int q = threadIdx.x + e * TX * TY;
-    make_entry<T>(g, q < LY * LX ? q : 0, i0, j0, en[e]);
+    const int q = (int)threadIdx.x + e * TX * TY;
+    make_entry<T>(g, q < LY * LX ? q : LY * LX - 1, i0, j0, en[e]);
   }
   // own position: which unknowns exist and the fixed sides (z parts per layer),
   // as bits of one vector register
   unsigned own = 0u;
+  bool plain;                            // every lane: all three unknowns, none held
   {
     const bool in = i <= nx && j <= ny;
     own |= in ? kIn : 0u;
     own |= (in && j < ny) ? kOkx : 0u;
     own |= (in && i < nx) ? kOky : 0u;
     own |= (in && i < nx && j < ny) ? kOkz : 0u;
-    own |= ((i == 0 && g.fixn[0]) || (i == nx && g.fixn[1])) ? kFixx : 0u;
-    own |= ((j == 0 && g.fixn[2]) || (j == ny && g.fixn[3])) ? kFixy : 0u;
+    const bool fx = (i == 0 && g.fixn[0]) || (i == nx && g.fixn[1]);
+    const bool fy = (j == 0 && g.fixn[2]) || (j == ny && g.fixn[3]);
+    own |= fx ? kFixx : 0u;
+    own |= fy ? kFixy : 0u;
+    plain = __builtin_amdgcn_ballot_w64(!(i < nx && j < ny) || fx || fy) == 0;
     // face-row duty (j = ny): the last wave, lane l takes position i0 + l
     const bool yface = j0 + TY == ny && wave == TY - 1 && i <= nx;
     own |= yface ? kYface : 0u;
@@ -342,19 +373,24 @@ __global__ __launch_bounds__(TX * TY) void el3d_stream_kernel(ElGeom g, ElSweep<
     own |= xface ? kXface : 0u;
     own |= (xface && ej < ny) ? kXfok : 0u;
   }
-  const unsigned pl32 = (unsigned)pl;    // a component holds fewer than 2^31 values
-  const unsigned S32 = (unsigned)S;
-  const unsigned pxy = (unsigned)(j * g.px + i);
-  const unsigned pfxy = (unsigned)(ny * g.px + i);
-  const unsigned pexy = (unsigned)((j0 + (int)threadIdx.x) * g.px + nx);
+  const bool edge_duty = (i0 + TX == nx && wave == 0) || (j0 + TY == ny && wave == TY - 1);
+  plain = plain && g.pins == nullptr;
+  // in-layer byte offsets of the own position (a valid slot for every lane, so the
+  // loads need no guard), of the face-row slot and of the face-column slot
+  const unsigned po = (own & kIn) ? (unsigned)(j * g.px + i) * W : 0u;
+  const unsigned pfo = (own & kYface) ? (unsigned)(ny * g.px + i) * W : 0u;
+  const unsigned peo = (own & kXface) ? (unsigned)((j0 + (int)threadIdx.x) * g.px + nx) * W : 0u;
+  // LDS indices of the face-column and face-row slots (a valid index for every lane)
+  const int qxe = (own & kXface) ? (1 + (int)threadIdx.x) * LX + XA : 0;
+  const int qye = (own & kYface) ? (TY + 1) * LX + a : 0;
   const int kend = (tz == ntiles / txy - 1) ? nz + 1 : k0 + KZ;
   // prologue: planes k0-1 (into buffer 1) and k0 (buffer 0); xz/yz shear at z = k0
   // into buffer 0; sigma_zz of the own cell at k0-1; plane k0+1 fetched ahead
   Plane<T, TY> P;
   fetch_plane<T, TY>(g, ux, uy, uz, A.E, S, SE, en, k0 - 1, P);
-  store_plane<T, TY>(P, en, 1, sm);
+  store_plane<T, TY>(g, P, en, k0 - 1, 1, sm);
   fetch_plane<T, TY>(g, ux, uy, uz, A.E, S, SE, en, k0, P);
-  store_plane<T, TY>(P, en, 0, sm);
+  store_plane<T, TY>(g, P, en, k0, 0, sm);
   if (done) return;   // uniform over the workgroup, before its first barrier
   __syncthreads();
   fetch_plane<T, TY>(g, ux, uy, uz, A.E, S, SE, en, k0 + 1, P);
@@ -363,131 +399,154 @@ __global__ __launch_bounds__(TX * TY) void el3d_stream_kernel(ElGeom g, ElSweep<
     const bool az = edge_ok(k0, nz, g.clamp[4], g.clamp[5], wz);
 #pragma unroll
     for (int e = 0; e < NE; ++e) {
-      if (e > 0 && (int)threadIdx.x + e * TX * TY >= LY * LX) continue;
-      xz_yz_entry<T, TY>(en[e], 1, 0, 0, az, wz, rh, mu0, sm);
+      if (!wave_has_entry<TY>(e)) continue;
+      xz_yz_entry<T, TY>(en[e], 1, 0, 0, az ? c25 : T(0), wz ? T(2) : T(1), rh, sm);
     }
   }
   T szz_prev = own_szz<T, TY>(sm, a, b, 1, 0, rh, lam0, mu0);
   __syncthreads();
   double acc = 0.0;
+  const int qo = b * LX + a;
   // one layer; the buffer parity is a compile-time constant (the loop below is
   // unrolled by two), so every LDS access has a constant offset
   auto layer = [&](auto parity, int k) {
     constexpr int cur = decltype(parity)::value;
     constexpr int up = cur ^ 1;
     // plane k+1 into LDS (its buffer was last read before the previous barrier)
-    store_plane<T, TY>(P, en, up, sm);
+    store_plane<T, TY>(g, P, en, k + 1, up, sm);
     // own velocity / right-hand side of layer k (issued early, used after the stresses)
-    const unsigned kS = (unsigned)k * S32;
-    const unsigned p = kS + pxy;
-    const bool in_z = k < nz;
-    const unsigned okm = in_z ? (kOkx | kOky | kOkz) : kOkz;
-    T vv[3], bb[3];
+    const long kS = k * S;
+    const T* vb = A.v + kS;
+    const T* bb = A.b + kS;
+    T vv[3], bv[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      const bool okc = (own & okm & (kOkx << c)) != 0u;
       vv[c] = T(0);
-      if ((MODE == kSweep || MODE == kCheck) && okc) vv[c] = A.v[c * pl32 + p];
-      bb[c] = okc ? A.b[c * pl32 + p] : T(0);
+      if (MODE == kSweep || MODE == kCheck) vv[c] = ldo(vb + c * pl, po);
+      bv[c] = ldo(bb + c * pl, po);
     }
-    const unsigned pe = kS + pexy;
-    const bool xok = in_z && (own & kXfok) != 0u;
-    T vxe = T(0), bxe = T(0);
-    if (xok) {
-      if (MODE == kSweep || MODE == kCheck) vxe = A.v[pe];
-      bxe = A.b[pe];
-    }
-    const unsigned pf = kS + pfxy;
-    const bool yok = in_z && (own & kYfok) != 0u;
-    T vye = T(0), bye = T(0);
-    if (yok) {
-      if (MODE == kSweep || MODE == kCheck) vye = A.v[pl32 + pf];
-      bye = A.b[pl32 + pf];
+    T vxe = T(0), bxe = T(0), vye = T(0), bye = T(0);
+    if (edge_duty) {
+      if (MODE == kSweep || MODE == kCheck) {
+        vxe = ldo(vb, peo);
+        vye = ldo(vb + pl, pfo);
+      }
+      bxe = ldo(bb, peo);
+      bye = ldo(bb + pl, pfo);
     }
     __syncthreads();
     // fetch plane k+2 while this layer computes
     if (k + 1 < kend) fetch_plane<T, TY>(g, ux, uy, uz, A.E, S, SE, en, k + 2, P);
-    const T uo[3] = {sm.u[cur][0][b][a], sm.u[cur][1][b][a], sm.u[cur][2][b][a]};
-    const T uxe = xok ? sm.u[cur][0][1 + threadIdx.x][XA] : T(0);
-    const T uye = yok ? sm.u[cur][1][TY + 1][a] : T(0);
+    const T uo[3] = {(&sm.u[cur][0][0][0])[qo], (&sm.u[cur][1][0][0])[qo], (&sm.u[cur][2][0][0])[qo]};
+    T uxe = T(0), uye = T(0);
+    if (edge_duty) {
+      uxe = (&sm.u[cur][0][0][0])[qxe];
+      uye = (&sm.u[cur][1][0][0])[qye];
+    }
     // normal stresses (cells of layer k) and xy shear (layer k), then the xz/yz
-    // shear planes at z = k+1
+    // shear planes at z = k+1; entries whose results no residual reads (first or
+    // last row and column) compute them all the same
+    const T cxy = k < nz ? c25 : T(0);
     bool wz = false;
     const bool az = edge_ok(k + 1, nz, g.clamp[4], g.clamp[5], wz);
+    const T cz = az ? c25 : T(0);
+    const T s1 = wz ? T(2) : T(1);
+    const T* U0 = &sm.u[cur][0][0][0];
+    const T* U1 = &sm.u[cur][1][0][0];
+    const T* U2 = &sm.u[cur][2][0][0];
+    const T* U2u = &sm.u[up][2][0][0];
+    const T* EC = &sm.e[cur][0][0];
 #pragma unroll
     for (int e = 0; e < NE; ++e) {
-      if (e > 0 && (int)threadIdx.x + e * TX * TY >= LY * LX) continue;
-      const int eb = en[e].eb, ea = en[e].ea;
-      T sxx = T(0), syy = T(0), txy_ = T(0);
-      if (en[e].has(kNrm) && eb + 1 < LY) {
-        const T ev = sm.e[cur][eb][ea];
-        const T exx = (sm.u[cur][0][eb][ea + 1] - sm.u[cur][0][eb][ea]) * rh;
-        const T eyy = (sm.u[cur][1][eb + 1][ea] - sm.u[cur][1][eb][ea]) * rh;
-        const T ezz = (sm.u[up][2][eb][ea] - sm.u[cur][2][eb][ea]) * rh;
-        T szz;
-        el3d::normal_stress<T>(ev * lam0, T(2) * (ev * mu0), exx, eyy, ezz, sxx, syy, szz);
-      }
-      if (en[e].has(kShr)) {
-        const T m = el3d::edge_modulus<T>(mu0, sm.e[cur][eb - 1][ea - 1], sm.e[cur][eb - 1][ea],
-                                          sm.e[cur][eb][ea - 1], sm.e[cur][eb][ea], in_z && en[e].has(kAxy),
-                                          en[e].has(kWxy));
-        const T gam = el3d::shear_strain<T>(sm.u[cur][0][eb][ea], sm.u[cur][0][eb - 1][ea], sm.u[cur][1][eb][ea],
-                                            sm.u[cur][1][eb][ea - 1], rh);
-        txy_ = m * gam;
-      }
-      sm.sxx[eb][ea] = sxx;
-      sm.syy[eb][ea] = syy;
-      sm.txy[eb][ea] = txy_;
-      xz_yz_entry<T, TY>(en[e], cur, up, up, az, wz, rh, mu0, sm);
+      if (!wave_has_entry<TY>(e)) continue;
+      const int q = en[e].q;
+      const T ev = EC[q];
+      const T exx = (U0[q + 1] - U0[q]) * rh;
+      const T eyy = (U1[q + LX] - U1[q]) * rh;
+      const T ezz = (U2u[q] - U2[q]) * rh;
+      T sxx, syy, szz;
+      el3d::normal_stress<T>(ev * lam0, T(2) * (ev * mu0), exx, eyy, ezz, sxx, syy, szz);
+      const T m = (cxy * (((EC[q - LX - 1] + EC[q - LX]) + EC[q - 1]) + ev)) * en[e].fxy;
+      const T gam = el3d::shear_strain<T>(U0[q], U0[q - LX], U1[q], U1[q - 1], rh);
+      (&sm.sxx[0][0])[q] = sxx;
+      (&sm.syy[0][0])[q] = syy;
+      (&sm.szz[0][0])[q] = szz;
+      (&sm.txy[0][0])[q] = m * gam;
+      xz_yz_entry<T, TY>(en[e], cur, up, up, cz, s1, rh, sm);
     }
-    const T szz_cur = own_szz<T, TY>(sm, a, b, cur, up, rh, lam0, mu0);
     __syncthreads();
     // residuals and update of the own position at layer k (reads stress planes only)
-    if (own & kIn) {
-      T rr[3];
-      rr[0] = el3d::residual<T>(bb[0], h2, sm.sxx[b][a], sm.sxx[b][a - 1], sm.txy[b + 1][a], sm.txy[b][a],
-                                sm.txz[up][b][a], sm.txz[cur][b][a]);
-      rr[1] = el3d::residual<T>(bb[1], h2, sm.syy[b][a], sm.syy[b - 1][a], sm.txy[b][a + 1], sm.txy[b][a],
-                                sm.tyz[up][b][a], sm.tyz[cur][b][a]);
-      rr[2] = el3d::residual<T>(bb[2], h2, szz_cur, szz_prev, sm.txz[cur][b][a + 1], sm.txz[cur][b][a],
-                                sm.tyz[cur][b + 1][a], sm.tyz[cur][b][a]);
-      const bool fixz = (k == 0 && g.fixn[4]) || (k == nz && g.fixn[5]);
+    const T* SXX = &sm.sxx[0][0];
+    const T* SYY = &sm.syy[0][0];
+    const T* TXY = &sm.txy[0][0];
+    const T* TXZc = &sm.txz[cur][0][0];
+    const T* TXZu = &sm.txz[up][0][0];
+    const T* TYZc = &sm.tyz[cur][0][0];
+    const T* TYZu = &sm.tyz[up][0][0];
+    const T szz_cur = (&sm.szz[0][0])[qo];
+    T rr[3];
+    rr[0] = el3d::residual<T>(bv[0], h2, SXX[qo], SXX[qo - 1], TXY[qo + LX], TXY[qo], TXZu[qo], TXZc[qo]);
+    rr[1] = el3d::residual<T>(bv[1], h2, SYY[qo], SYY[qo - LX], TXY[qo + 1], TXY[qo], TYZu[qo], TYZc[qo]);
+    rr[2] = el3d::residual<T>(bv[2], h2, szz_cur, szz_prev, TXZc[qo + 1], TXZc[qo], TYZc[qo + LX], TYZc[qo]);
+    Out<T, MODE> o[3];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const unsigned gi = c * pl32 + p;
-        if ((own & okm & (kOkx << c)) == 0u) {
-          zero_slot<T, MODE>(A, gi);
-          continue;
+    for (int c = 0; c < 3; ++c) {
+      o[c].v = MODE == kRefine ? nullptr : A.v + c * pl + kS;
+      o[c].u = MODE == kSweep || MODE == kCheck ? A.uout + c * pl + kS : nullptr;
+      o[c].r32 = MODE == kRefine ? A.b32 + c * pl + kS : nullptr;
+    }
+    const bool fixz = (k == 0 && g.fixn[4]) || (k == nz && g.fixn[5]);
+    if (plain && k < nz && !fixz) {
+      // every lane of the wave owns three free unknowns
+#pragma unroll
+      for (int c = 0; c < 3; ++c) finish<T, MODE>(o[c], po, false, rr[c], uo[c], vv[c], ca, cc, dt, acc);
+    } else {
+      unsigned ow = own;
+      asm volatile("" : "+v"(ow));   // re-derive the lane tests here, not across the loop
+      if (ow & kIn) {
+        const unsigned okm = k < nz ? (kOkx | kOky | kOkz) : kOkz;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          if ((ow & okm & (kOkx << c)) == 0u) {
+            zero_slot<T, MODE>(o[c], po);
+            continue;
+          }
+          bool fixc = c == 0 ? (ow & kFixx) != 0u : (c == 1 ? (ow & kFixy) != 0u : fixz);
+          if (g.pins != nullptr) fixc = fixc || pinned3s(g.pins, c * pl + kS + po / W);
+          finish<T, MODE>(o[c], po, fixc, rr[c], uo[c], vv[c], ca, cc, dt, acc);
         }
-        const bool fixc = c == 0 ? (own & kFixx) != 0u : (c == 1 ? (own & kFixy) != 0u : fixz);
-        finish<T, MODE>(A, gi, fixc || pinned3s(g.pins, gi), rr[c], uo[c], vv[c], ca, cc, dt, acc);
       }
     }
-    // the face column i = nx: u_x only (u_y, u_z slots are padding)
-    if (own & kXface) {
-      const int eb = 1 + (int)threadIdx.x;
-      if (xok) {
-        const T r = el3d::residual<T>(bxe, h2, sm.sxx[eb][XA], sm.sxx[eb][XA - 1], sm.txy[eb + 1][XA],
-                                      sm.txy[eb][XA], sm.txz[up][eb][XA], sm.txz[cur][eb][XA]);
-        finish<T, MODE>(A, pe, g.fixn[1] || pinned3s(g.pins, pe), r, uxe, vxe, ca, cc, dt, acc);
-      } else {
-        zero_slot<T, MODE>(A, pe);
+    if (edge_duty) {
+      unsigned ow = own;
+      asm volatile("" : "+v"(ow));
+      // the face column i = nx: u_x only (u_y, u_z slots are padding)
+      if (ow & kXface) {
+        const int eb = 1 + (int)threadIdx.x;
+        if (k < nz && (ow & kXfok) != 0u) {
+          const T r = el3d::residual<T>(bxe, h2, sm.sxx[eb][XA], sm.sxx[eb][XA - 1], sm.txy[eb + 1][XA],
+                                        sm.txy[eb][XA], sm.txz[up][eb][XA], sm.txz[cur][eb][XA]);
+          finish<T, MODE>(o[0], peo, g.fixn[1] || pinned3s(g.pins, kS + peo / W), r, uxe, vxe, ca, cc, dt, acc);
+        } else {
+          zero_slot<T, MODE>(o[0], peo);
+        }
+        zero_slot<T, MODE>(o[1], peo);
+        zero_slot<T, MODE>(o[2], peo);
       }
-      zero_slot<T, MODE>(A, pl32 + pe);
-      zero_slot<T, MODE>(A, 2 * pl32 + pe);
-    }
-    // the face row j = ny: u_y only (u_x, u_z slots are padding)
-    if (own & kYface) {
-      const int fb = TY + 1;
-      if (yok) {
-        const T r = el3d::residual<T>(bye, h2, sm.syy[fb][a], sm.syy[fb - 1][a], sm.txy[fb][a + 1],
-                                      sm.txy[fb][a], sm.tyz[up][fb][a], sm.tyz[cur][fb][a]);
-        finish<T, MODE>(A, pl32 + pf, g.fixn[3] || pinned3s(g.pins, pl32 + pf), r, uye, vye, ca, cc, dt, acc);
-      } else {
-        zero_slot<T, MODE>(A, pl32 + pf);
+      // the face row j = ny: u_y only (u_x, u_z slots are padding)
+      if (ow & kYface) {
+        const int fb = TY + 1;
+        if (k < nz && (ow & kYfok) != 0u) {
+          const T r = el3d::residual<T>(bye, h2, sm.syy[fb][a], sm.syy[fb - 1][a], sm.txy[fb][a + 1],
+                                        sm.txy[fb][a], sm.tyz[up][fb][a], sm.tyz[cur][fb][a]);
+          finish<T, MODE>(o[1], pfo, g.fixn[3] || pinned3s(g.pins, pl + kS + pfo / W), r, uye, vye, ca, cc, dt,
+                          acc);
+        } else {
+          zero_slot<T, MODE>(o[1], pfo);
+        }
+        zero_slot<T, MODE>(o[0], pfo);
+        zero_slot<T, MODE>(o[2], pfo);
       }
-      zero_slot<T, MODE>(A, pf);
-      zero_slot<T, MODE>(A, 2 * pl32 + pf);
     }
     szz_prev = szz_cur;
     // the next store writes the plane read before the barrier above, and the
