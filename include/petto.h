@@ -259,15 +259,17 @@ int32_t petto_blocking(const petto_ctx *ctx);
 
 /* Tiling of the 3D elastic sweeps (streamed along z, Eqs. 3.6 and 3.12 in 3D):
  * t = 1: columns of 64 x 8 positions (FP64: 64 x 4) through 8 layers, the fewest
- * halo bytes; t = 2: columns of 64 x 4 positions through 4 layers, more
- * workgroups for small grids; t = 0: choose as at creation (t = 1 when it gives
- * at least two workgroups per compute unit, else t = 2).  Results are
- * bit-identical for both tilings except the order of the FP64 residual-norm sum.
- * Errors: PETTO_ERR_INVALID for other values or a context that is not 3D elastic.
- * Cached launch graphs are dropped. */
+ * halo bytes; t = 2: columns of 64 x 4 positions through 4 layers and t = 3:
+ * through 2 layers, more workgroups for small grids; t = 0: choose as at
+ * creation (t = 1 when it gives at least two workgroups per compute unit, else
+ * whichever of t = 2 and t = 3 needs fewer rounds of resident workgroups times
+ * staged planes per workgroup).  Results are bit-identical for all tilings
+ * except the order of the FP64 residual-norm sum.  Errors: PETTO_ERR_INVALID for
+ * other values or a context that is not 3D elastic.  Cached launch graphs are
+ * dropped. */
 petto_status petto_set_tile3d(petto_ctx *ctx, int32_t t);
 
-/* The 3D tiling in use (1 or 2; 0 for a NULL context). */
+/* The 3D tiling in use (1, 2 or 3; 0 for a NULL context). */
 int32_t petto_tile3d(const petto_ctx *ctx);
 
 /* Time the context's dominant sweep kernel (the relaxation launch of Eq. 3.12 /

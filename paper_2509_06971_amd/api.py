@@ -185,7 +185,7 @@ class Context:
         return int(self.lib.petto_blocking(self.h))
 
     def set_tile3d(self, t):
-        """Tiling of the 3D elastic sweeps: 1 large columns, 2 small, 0 automatic."""
+        """Tiling of the 3D elastic sweeps: 1 large columns, 2 small, 3 short, 0 automatic."""
         L.check(self.lib.petto_set_tile3d(self.h, int(t)))
 
     def tile3d(self):

@@ -563,14 +563,17 @@ __global__ __launch_bounds__(TX * TY, 4) void el3d_stream_kernel(ElGeom g, ElSwe
   }
 }
 
-// Two tilings per precision: columns of 64 x TY positions streamed through KZ
-// layers.  The large one moves the fewest halo bytes; the small one gives
-// small grids enough workgroups to fill the chip.
+// Three tilings per precision: columns of 64 x TY positions streamed through KZ
+// layers.  The large one moves the fewest halo bytes; the smaller ones give
+// small grids enough workgroups to fill the chip (the shortest columns trade
+// more z-halo planes, mostly L2 hits, for twice the workgroups).
 template <typename T, int V> struct Cfg3;
 template <> struct Cfg3<float, 1> { static constexpr int TY = 8, KZ = 8; };
 template <> struct Cfg3<float, 2> { static constexpr int TY = 4, KZ = 4; };
+template <> struct Cfg3<float, 3> { static constexpr int TY = 4, KZ = 2; };
 template <> struct Cfg3<double, 1> { static constexpr int TY = 4, KZ = 8; };
 template <> struct Cfg3<double, 2> { static constexpr int TY = 4, KZ = 4; };
+template <> struct Cfg3<double, 3> { static constexpr int TY = 4, KZ = 2; };
 
 template <typename T, int V>
 void tiles_s(const ElGeom& g, int& tx, int& ty, int& tz) {
@@ -599,24 +602,36 @@ int launch_v(const ElGeom& g, const ElSweep<T>& a, hipStream_t s) {
 }  // namespace
 
 int el3d_tiles_prec(const ElGeom& g, bool fp64) {
-  if (fp64) return g.tile3d == 2 ? count_s<double, 2>(g) : count_s<double, 1>(g);
-  return g.tile3d == 2 ? count_s<float, 2>(g) : count_s<float, 1>(g);
+  if (fp64) return g.tile3d == 3 ? count_s<double, 3>(g) : g.tile3d == 2 ? count_s<double, 2>(g) : count_s<double, 1>(g);
+  return g.tile3d == 3 ? count_s<float, 3>(g) : g.tile3d == 2 ? count_s<float, 2>(g) : count_s<float, 1>(g);
 }
 
 int el3d_tiles(const ElGeom& g) {
-  const int c[4] = {count_s<float, 1>(g), count_s<float, 2>(g), count_s<double, 1>(g), count_s<double, 2>(g)};
+  const int c[6] = {count_s<float, 1>(g),  count_s<float, 2>(g),  count_s<float, 3>(g),
+                    count_s<double, 1>(g), count_s<double, 2>(g), count_s<double, 3>(g)};
   int m = 0;
   for (int x : c) m = x > m ? x : m;
   return m;
 }
 
+// The large tiling when it gives two resident workgroups per compute unit;
+// otherwise, of the two 64 x 4 column tilings, the one with the smaller modelled
+// time: rounds of resident workgroups (four of 256 threads per unit in FP32, two
+// in FP64, bounded by registers) times the planes a workgroup stages (its layers
+// plus two for the prologue).  Ties go to the longer columns (fewer halo bytes).
 int el3d_choose_tiling(const ElGeom& g, bool fp64, int ncu) {
   const int large = fp64 ? count_s<double, 1>(g) : count_s<float, 1>(g);
-  return large >= 2 * ncu ? 1 : 2;
+  if (large >= 2 * ncu) return 1;
+  const long slots = (long)(fp64 ? 2 : 4) * ncu;
+  auto cost = [&](int count, int kz) { return ((count + slots - 1) / slots) * (kz + 2); };
+  const long c2 = fp64 ? cost(count_s<double, 2>(g), Cfg3<double, 2>::KZ) : cost(count_s<float, 2>(g), Cfg3<float, 2>::KZ);
+  const long c3 = fp64 ? cost(count_s<double, 3>(g), Cfg3<double, 3>::KZ) : cost(count_s<float, 3>(g), Cfg3<float, 3>::KZ);
+  return c3 < c2 ? 3 : 2;
 }
 
 template <typename T, int MODE>
 int launch_el3d(const ElGeom& g, const ElSweep<T>& a, hipStream_t s) {
+  if (g.tile3d == 3) return launch_v<T, 3, MODE>(g, a, s);
   return g.tile3d == 2 ? launch_v<T, 2, MODE>(g, a, s) : launch_v<T, 1, MODE>(g, a, s);
 }
 

@@ -1319,7 +1319,7 @@ petto_status petto_set_tile3d(petto_ctx* ctx, int32_t t) {
   if (ctx == nullptr) return fail(PETTO_ERR_INVALID, "ctx is NULL");
   if (ctx->physics != PETTO_ELASTIC || ctx->ndim != 3)
     return fail(PETTO_ERR_INVALID, "the 3D tiling applies to 3D elastic contexts");
-  if (t < 0 || t > 2) return fail(PETTO_ERR_INVALID, "unsupported 3D tiling %d", t);
+  if (t < 0 || t > 3) return fail(PETTO_ERR_INVALID, "unsupported 3D tiling %d", t);
   if (t == 0) t = el3d_choose_tiling(ctx->geom, ctx->prec == PETTO_FP64, ctx->ncu);
   ctx->geom.tile3d = t;
   destroy_graphs(ctx);

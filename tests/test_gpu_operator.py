@@ -22,7 +22,7 @@ def _elastic_cases():
 
 def _tilings(prob):
     """3D contexts: every sweep tiling; 2D: the default."""
-    return [1, 2] if prob.ndim == 3 else [None]
+    return [1, 2, 3] if prob.ndim == 3 else [None]
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
