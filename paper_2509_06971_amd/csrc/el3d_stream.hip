@@ -386,14 +386,20 @@ __global__ __launch_bounds__(TX * TY, 4) void el3d_stream_kernel(ElGeom g, ElSwe
   const int kend = (tz == ntiles / txy - 1) ? nz + 1 : k0 + KZ;
   // prologue: planes k0-1 (into buffer 1) and k0 (buffer 0); xz/yz shear at z = k0
   // into buffer 0; sigma_zz of the own cell at k0-1; plane k0+1 fetched ahead
-  Plane<T, TY> P;
+  // (the loads of all three planes are issued before the first wait, so the
+  // prologue costs one memory round trip)
+  Plane<T, TY> P, Q;
   fetch_plane<T, TY>(g, ux, uy, uz, A.E, S, SE, en, k0 - 1, P);
-  store_plane<T, TY>(g, P, en, k0 - 1, 1, sm);
-  fetch_plane<T, TY>(g, ux, uy, uz, A.E, S, SE, en, k0, P);
-  store_plane<T, TY>(g, P, en, k0, 0, sm);
+  fetch_plane<T, TY>(g, ux, uy, uz, A.E, S, SE, en, k0, Q);
+  {
+    Plane<T, TY> R;
+    fetch_plane<T, TY>(g, ux, uy, uz, A.E, S, SE, en, k0 + 1, R);
+    store_plane<T, TY>(g, P, en, k0 - 1, 1, sm);
+    store_plane<T, TY>(g, Q, en, k0, 0, sm);
+    P = R;
+  }
   if (done) return;   // uniform over the workgroup, before its first barrier
   __syncthreads();
-  fetch_plane<T, TY>(g, ux, uy, uz, A.E, S, SE, en, k0 + 1, P);
   {
     bool wz = false;
     const bool az = edge_ok(k0, nz, g.clamp[4], g.clamp[5], wz);
