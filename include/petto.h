@@ -204,7 +204,11 @@ size_t petto_field_offset(const petto_ctx *ctx, int32_t iprob, int32_t field);
  * velocity v (device, context precision, overwritten).  On return u holds the
  * relaxed state and info (host, nprob entries, may be NULL) the solve record.
  * Returns PETTO_OK if every design met tol, PETTO_NOT_CONVERGED if one hit max_iter,
- * PETTO_ERR_DIVERGED if one diverged.  Synchronous: returns after the GPU work. */
+ * PETTO_ERR_DIVERGED if one diverged.  Synchronous: returns after the GPU work,
+ * except for fixed-count stages called with info == NULL while sweep timing is
+ * off (replay_iters > 0, and the n_pt stage): those are only enqueued on stream,
+ * so with replay_iters > 0 the call returns PETTO_OK at once (divergence is then
+ * not reported; the device still stops a diverged design). */
 petto_status petto_apt_solve(petto_ctx *ctx, const void *phi, void *u, void *v,
                              const petto_apt_params *params, void *stream, petto_solve_info *info);
 
@@ -230,7 +234,9 @@ petto_status petto_phase_update(petto_ctx *ctx, void *phi, const void *grad_phi,
 
 /* One optimisation loop of Fig. 4: petto_apt_solve, petto_adjoint (w = u), then
  * petto_phase_update.  grad_phi (device) receives the sensitivity used;
- * compliance (device double[2*nprob], may be NULL) as in petto_adjoint. */
+ * compliance (device double[2*nprob], may be NULL) as in petto_adjoint.  With a
+ * fixed sweep count and sinfo == pinfo == NULL the whole loop is only enqueued on
+ * stream (no host wait), so successive calls run back to back on the GPU. */
 petto_status petto_step(petto_ctx *ctx, void *phi, void *u, void *v, void *grad_phi,
                         double *compliance, const petto_apt_params *ap,
                         const petto_phase_params *pp, void *stream,

@@ -161,20 +161,25 @@ class Context:
                                             C.byref(p), _stream(stream), infos))
         return [infos[i].as_dict() for i in range(self.nprob)] if info else None
 
-    def step(self, phi, u, v, grad, vol_frac, compliance=None, stream=None, apt=None, phase=None):
+    def step(self, phi, u, v, grad, vol_frac, compliance=None, stream=None, apt=None, phase=None, info=True):
+        """One design loop.  info=False asks for no solve / update records: with a
+        fixed sweep count the loop is then only enqueued (no host wait) and the two
+        record lists come back as None."""
         ap = self.apt_params(**(apt or {}))
         pp = self.phase_params(vol_frac, **(phase or {}))
         udt = torch.float64 if ap.refine else self.dtype
         comp = compliance if compliance is not None else torch.empty(2 * self.nprob, dtype=torch.float64,
                                                                      device="cuda")
-        si = (L.SolveInfo * self.nprob)()
-        pi = (L.PhaseInfo * self.nprob)()
+        si = (L.SolveInfo * self.nprob)() if info else None
+        pi = (L.PhaseInfo * self.nprob)() if info else None
         st = self.lib.petto_step(self.h, self._ptr(phi, self.dtype, self.nphase * self.ncell, "phi"),
                                  self._ptr(u, udt, self.nstate, "u"), self._ptr(v, self.dtype, self.nstate, "v"),
                                  self._ptr(grad, self.dtype, self.nphase * self.ncell, "grad"),
                                  self._ptr(comp, torch.float64, 2 * self.nprob, "compliance"),
                                  C.byref(ap), C.byref(pp), _stream(stream), si, pi)
         L.check(st)
+        if not info:
+            return st, None, None, comp
         return st, [si[i].as_dict() for i in range(self.nprob)], [pi[i].as_dict() for i in range(self.nprob)], comp
 
     def set_blocking(self, k):

@@ -209,29 +209,37 @@ struct PhaseArgs {
   long n;
   double h, alpha, gamma, dt_ac, target;
   int nblocks;
-  // the penalty / Cahn-Hilliard update
-  const double* total;      // sum of all stored phases of the old design, or nullptr (this phase alone)
-  double* work2;            // chemical potential mu (double)
-  double alpha_v, alpha_1, vol_frac, dt_ch, mobility;
   // regions (nullptr: every cell is a design cell)
   const uint8_t* region;    // PETTO_REGION_* per cell of this design
   int first;                // this is phase 0 (passive-solid cells hold it at 1)
-  double alpha_b;           // penalty model: void-region weight
 };
 template <typename T> void launch_phase_gmax(const PhaseArgs<T>& a, hipStream_t s);
 template <typename T> void launch_phase_step(const PhaseArgs<T>& a, hipStream_t s);
 template <typename T> void launch_phase_pass(const PhaseArgs<T>& a, hipStream_t s);
 template <typename T> void launch_phase_apply(const PhaseArgs<T>& a, hipStream_t s);
 int phase_blocks(long n);
-// The penalty update: max|g| and sum(phi) of the phase (into scal[0], scal[6]),
-// then phi' into work; then mu = w'(phi') - gamma lap(phi') into work2 and
-// phi = phi' + dt_ch D lap(mu), with the new mean into scal[4].
-template <typename T> void launch_penalty_prep(const PhaseArgs<T>& a, hipStream_t s);
-template <typename T> void launch_penalty_step(const PhaseArgs<T>& a, hipStream_t s);
-template <typename T> void launch_cahn_hilliard(const PhaseArgs<T>& a, hipStream_t s);
-// total[c] = sum over nphase stored phases (stride ncell) of phi[c]
+
+// The paper's penalty update and Cahn-Hilliard step for every stored phase of
+// one design, in five launches whatever the phase count.
 template <typename T>
-void launch_phase_total(const T* phi, long ncell, int nphase, long n, double* total, hipStream_t s);
+struct PenaltyArgs {
+  T* phi;                   // phase 0 of the design (in/out); phase m at + m * pstride
+  const T* g;               // sensitivity, same layout
+  long pstride;             // elements between phases (the context's cell count)
+  int nphase;
+  double* mu;               // chemical potential of phase m at + m * mstride (double)
+  long mstride;
+  double* partial;          // per block scratch, >= 3 * nphase * nblocks
+  double* scal;             // phase m: scal + 8 m ([0] max|g| [1] volume-penalty term
+                            // [3] its negative [4] new mean [6] sum phi [7] sum over the void region)
+  int nx, ny, nz, ndim;     // cells (nz = 1 in 2D)
+  long n;
+  double h, alpha, gamma, alpha_v, alpha_1, dt_ch, mobility, alpha_b;
+  double vol_frac[kMaxPhase];
+  const uint8_t* region;    // PETTO_REGION_* per cell, or nullptr
+  int nblocks;
+};
+template <typename T> void launch_penalty_update(const PenaltyArgs<T>& a, hipStream_t s);
 
 // out[2d] = sum of pfu over design d's tiles, out[2d+1] = the same for pen.
 void launch_dot_finalize(const double* pfu, const double* pen, const int* tile0, int ntile, int ndes,

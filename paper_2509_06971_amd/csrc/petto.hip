@@ -341,10 +341,19 @@ petto_status enqueue_block(petto_ctx* c, hipStream_t stream, bool use_graph, con
 // Run blocks until the finalize kernel reports every design done.  Two blocks are
 // kept in flight; a block enqueued after the stop finds the done flags set and its
 // kernels return at once.  Blocks timed (when enabled) are those up to the stop.
+// With last == nullptr (a fixed block count whose caller wants no report) the
+// blocks are only enqueued.
 petto_status run_blocks(petto_ctx* c, hipStream_t stream, bool use_graph, const std::vector<const void*>& key,
                         const std::function<void(hipStream_t)>& body, int sweeps_per_block, PollRecord* last,
                         long max_blocks) {
   PETTO_TRY(ensure_events(c));
+  if (last == nullptr) {
+    // a fixed count with nothing to report: enqueue every block and return; the
+    // host neither waits nor reads the poll ring (the finalize kernels still
+    // apply the stop rule on the device)
+    for (long b = 0; b < max_blocks; ++b) PETTO_TRY(enqueue_block(c, stream, use_graph, key, body));
+    return PETTO_OK;
+  }
   long launched = 0, checked = 0;
   std::vector<float> block_ms;
   for (;;) {
@@ -654,8 +663,8 @@ petto_status ensure_blocking(petto_ctx* c, hipStream_t s, int nchk) {
 // Plain relaxation in the context precision.
 template <typename T>
 petto_status solve_plain(petto_ctx* c, const void* phi, void* u, void* v, const petto_apt_params* ap,
-                         hipStream_t s, petto_solve_info* info) {
-  PETTO_TRY(material<T>(c, phi, s, false));
+                         hipStream_t s, petto_solve_info* info, bool material_ready) {
+  if (!material_ready) PETTO_TRY(material<T>(c, phi, s, false));
   const int replay = ap->replay_iters > 0;
   PETTO_TRY(setup(c, s, c->st, ap, replay ? -1.0 : ap->tol, replay, replay ? ap->replay_iters : ap->max_iter));
   launch_fill<T>(static_cast<T*>(v), c->nstate, T(0), s);
@@ -710,7 +719,11 @@ petto_status solve_plain(petto_ctx* c, const void* phi, void* u, void* v, const 
   PollRecord last{};
   // the finalize of the last block marks the stop at max_iter (replay: exactly there)
   const long max_blocks = replay ? ap->replay_iters / nchk : ((long)ap->max_iter + nchk - 1) / nchk;
-  PETTO_TRY(run_blocks(c, s, ap->use_graph != 0, key, body, nchk, &last, max_blocks));
+  // a fixed count whose caller wants no report runs without the host (unless the
+  // sweep blocks are being timed)
+  const bool detached = replay && info == nullptr && !c->timing;
+  PETTO_TRY(run_blocks(c, s, ap->use_graph != 0, key, body, nchk, detached ? nullptr : &last, max_blocks));
+  if (detached) return PETTO_OK;
   std::vector<SolveState> h;
   PETTO_TRY(read_states(c, c->st, h, s));
   if (info) {
@@ -733,8 +746,8 @@ petto_status solve_plain(petto_ctx* c, const void* phi, void* u, void* v, const 
 // check_every FP32 sweeps on K d = r with the velocity carried over.  In exact
 // arithmetic the pair (u + d, v) follows the plain iteration.
 petto_status solve_refine(petto_ctx* c, const void* phi, void* u, void* v, const petto_apt_params* ap,
-                          hipStream_t s, petto_solve_info* info) {
-  PETTO_TRY(material<float>(c, phi, s, true));
+                          hipStream_t s, petto_solve_info* info, bool material_ready) {
+  if (!material_ready) PETTO_TRY(material<float>(c, phi, s, true));
   PETTO_TRY(setup(c, s, c->st, ap, ap->tol, 0, ap->max_iter));
   PETTO_TRY(ensure_blocking(c, s, ap->check_every));
   double* u64 = static_cast<double*>(u);
@@ -787,7 +800,11 @@ petto_status solve_refine(petto_ctx* c, const void* phi, void* u, void* v, const
   // a block checks the state its predecessors produced: one block more than the
   // sweeps need, for the check that stops at max_iter
   const long max_blocks = ((long)ap->max_iter + nchk - 1) / nchk + 1;
-  PETTO_TRY(run_blocks(c, s, ap->use_graph != 0, key, body, nchk, &last, max_blocks));
+  // tol = 0 (a fixed-count stage) never stops early: with no report wanted, the
+  // host need not follow it
+  const bool detached = !(ap->tol > 0.0) && info == nullptr && !c->timing;
+  PETTO_TRY(run_blocks(c, s, ap->use_graph != 0, key, body, nchk, detached ? nullptr : &last, max_blocks));
+  if (detached) return PETTO_OK;
   std::vector<SolveState> h;
   PETTO_TRY(read_states(c, c->st, h, s));
   if (info) {
@@ -851,57 +868,47 @@ petto_status phase_update_impl(petto_ctx* c, void* phi, const void* grad, const 
   const T* g = static_cast<const T*>(grad);
   const int passes = pp->bisect_passes > 0 ? pp->bisect_passes : 9;
   if (pp->model == PETTO_UPDATE_PENALTY_CH) {
-    // per phase phi', then mu, then the partition sum of the old design
-    if (c->pen_work == nullptr) PETTO_TRY(dalloc_t(c, &c->pen_work, (size_t)(c->nphase + 2) * c->max_cells));
-    double* total = c->pen_work + (long)(c->nphase + 1) * c->max_cells;
+    // every stored phase of a design per launch: totals, phi' formed on the fly,
+    // mu per phase into the work buffer, then the Cahn-Hilliard step in place
+    if (c->pen_work == nullptr) PETTO_TRY(dalloc_t(c, &c->pen_work, (size_t)c->nphase * c->max_cells));
     for (int d = 0; d < c->nprob; ++d) {
       const CellRange& R = c->h_ranges[d];
       const double h = R.h;
-      const bool partition = pp->alpha_1 != 0.0 && c->nphase > 1;
-      if (partition) launch_phase_total<T>(ph + R.off, c->ncell, c->nphase, R.n, total, s);
-      std::vector<PhaseArgs<T>> args(c->nphase);
-      for (int m = 0; m < c->nphase; ++m) {
-        PhaseArgs<T>& a = args[m];
-        a.phi = ph + (long)m * c->ncell + R.off;
-        a.g = g + (long)m * c->ncell + R.off;
-        a.total = partition ? total : nullptr;
-        a.work = c->pen_work + (long)m * c->max_cells;
-        a.work2 = c->pen_work + (long)c->nphase * c->max_cells;
-        a.partial = c->phase_partial;
-        a.scal = c->phase_scal + (long)(kMaxPhase * d + m) * 8;
-        a.nx = R.nx;
-        a.ny = R.ny;
-        a.nz = R.nz;
-        a.ndim = c->ndim;
-        a.n = R.n;
-        a.h = h;
-        a.alpha = pp->alpha_h;
-        a.gamma = pp->gamma;
-        a.alpha_v = pp->alpha_v;
-        a.alpha_1 = pp->alpha_1;
-        a.vol_frac = pp->vol_frac[m];
-        a.mobility = pp->mobility > 0.0 ? pp->mobility : 1.0;
-        if (pp->dt_ch > 0.0) {
-          a.dt_ch = pp->dt_ch;
-        } else {
-          // the printed 500 h^4, capped at 0.9 of the explicit step's stability
-          // limit 2 / (D lam (pi^2/32 + gamma lam)), lam = 4 d / h^2
-          const double pi = 3.141592653589793;
-          const double lam = 4.0 * c->ndim / (h * h);
-          const double limit = 2.0 / (a.mobility * lam * (pi * pi / 32.0 + pp->gamma * lam));
-          a.dt_ch = std::fmin(500.0 * h * h * h * h, 0.9 * limit);
-        }
-        a.region = c->d_region != nullptr ? c->d_region + R.off : nullptr;
-        a.first = m == 0;
-        a.alpha_b = pp->alpha_b;
-        a.nblocks = phase_blocks(R.n);
+      PenaltyArgs<T> a{};
+      a.phi = ph + R.off;
+      a.g = g + R.off;
+      a.pstride = c->ncell;
+      a.nphase = c->nphase;
+      a.mu = c->pen_work;
+      a.mstride = c->max_cells;
+      a.partial = c->phase_partial;
+      a.scal = c->phase_scal + (long)kMaxPhase * d * 8;
+      a.nx = R.nx;
+      a.ny = R.ny;
+      a.nz = R.nz;
+      a.ndim = c->ndim;
+      a.n = R.n;
+      a.h = h;
+      a.alpha = pp->alpha_h;
+      a.gamma = pp->gamma;
+      a.alpha_v = pp->alpha_v;
+      a.alpha_1 = pp->alpha_1;
+      for (int m = 0; m < kMaxPhase; ++m) a.vol_frac[m] = pp->vol_frac[m];
+      a.mobility = pp->mobility > 0.0 ? pp->mobility : 1.0;
+      if (pp->dt_ch > 0.0) {
+        a.dt_ch = pp->dt_ch;
+      } else {
+        // the printed 500 h^4, capped at 0.9 of the explicit step's stability
+        // limit 2 / (D lam (pi^2/32 + gamma lam)), lam = 4 d / h^2
+        const double pi = 3.141592653589793;
+        const double lam = 4.0 * c->ndim / (h * h);
+        const double limit = 2.0 / (a.mobility * lam * (pi * pi / 32.0 + pp->gamma * lam));
+        a.dt_ch = std::fmin(500.0 * h * h * h * h, 0.9 * limit);
       }
-      // every phase's step from the old design, then the Cahn-Hilliard steps
-      for (int m = 0; m < c->nphase; ++m) {
-        launch_penalty_prep<T>(args[m], s);
-        launch_penalty_step<T>(args[m], s);
-      }
-      for (int m = 0; m < c->nphase; ++m) launch_cahn_hilliard<T>(args[m], s);
+      a.region = c->d_region != nullptr ? c->d_region + R.off : nullptr;
+      a.alpha_b = pp->alpha_b;
+      a.nblocks = phase_blocks(R.n);
+      launch_penalty_update<T>(a, s);
       HIP_TRY(hipGetLastError());
     }
   } else {
@@ -1339,12 +1346,13 @@ petto_status petto_apt_solve(petto_ctx* ctx, const void* phi, void* u, void* v, 
     ctx->timed_ms = 0.0;
     ctx->timed_sweeps = 0;
   }
-  auto stage = [&](const petto_apt_params* p, petto_solve_info* inf) -> petto_status {
-    if (p->refine) return solve_refine(ctx, phi, u, v, p, s, inf);
-    if (ctx->prec == PETTO_FP64) return solve_plain<double>(ctx, phi, u, v, p, s, inf);
-    return solve_plain<float>(ctx, phi, u, v, p, s, inf);
+  // (the second stage runs on the moduli the first one formed from the same design)
+  auto stage = [&](const petto_apt_params* p, petto_solve_info* inf, bool ready) -> petto_status {
+    if (p->refine) return solve_refine(ctx, phi, u, v, p, s, inf, ready);
+    if (ctx->prec == PETTO_FP64) return solve_plain<double>(ctx, phi, u, v, p, s, inf, ready);
+    return solve_plain<float>(ctx, phi, u, v, p, s, inf, ready);
   };
-  const petto_status s1 = stage(params, info);
+  const petto_status s1 = stage(params, info, false);
   if (s1 < 0 || params->n_pt == 0) return s1;
   // the hybrid schedule's second stage: n_pt plain PT sweeps (theta = 0: the
   // velocity plays no part), a fixed count without the stop rule
@@ -1363,7 +1371,7 @@ petto_status petto_apt_solve(petto_ctx* ctx, const void* phi, void* u, void* v, 
     q.max_iter = params->n_pt;
   }
   std::vector<petto_solve_info> pt(ctx->nprob);
-  const petto_status s2 = stage(&q, pt.data());
+  const petto_status s2 = stage(&q, info ? pt.data() : nullptr, true);
   if (s2 < 0) return s2;
   if (info) {
     for (int d = 0; d < ctx->nprob; ++d) {

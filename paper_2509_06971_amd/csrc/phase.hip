@@ -200,56 +200,87 @@ __global__ void volume_final_kernel(const double* partial, int nb, double* scal,
 }
 
 // ---- the paper's own update: penalty step (Eq. 2.13, normalised sensitivity of
-// Section 3.1) and one explicit Cahn-Hilliard step (Eq. 2.14)
+// Section 3.1) and one explicit Cahn-Hilliard step (Eq. 2.14), every stored
+// phase of a design in each launch.  The per-phase block partials and final sums
+// keep the cell-to-thread mapping and summation order of a one-phase launch.
 
+// max|g_m|, sum phi_m and (with the void-region term) sum of phi_m over the void
+// region; blockIdx.y is the phase
 template <typename T>
-__global__ __launch_bounds__(kBlock) void sum_kernel(PhaseArgs<T> A) {
+__global__ __launch_bounds__(kBlock) void pen_reduce_kernel(PenaltyArgs<T> A) {
   __shared__ double red[kBlock / kWave];
-  double acc = 0.0;
-  for (long c = (long)blockIdx.x * kBlock + threadIdx.x; c < A.n; c += (long)gridDim.x * kBlock)
-    acc += (double)A.phi[c];
-  const double t = block_sum(acc, red);
-  if (threadIdx.x == 0) A.partial[blockIdx.x] = t;
-}
-
-__global__ void sum_final_kernel(const double* partial, int nb, double* scal, int slot) {
-  double s = 0.0;
-  for (int b = threadIdx.x; b < nb; b += kWave) s += partial[b];
-  s = wave_sum(s);
-  if (threadIdx.x == 0) scal[slot] = s;
-}
-
-// sum of the phase over the void region
-template <typename T>
-__global__ __launch_bounds__(kBlock) void region_sum_kernel(PhaseArgs<T> A) {
-  __shared__ double red[kBlock / kWave];
-  double acc = 0.0;
-  for (long c = (long)blockIdx.x * kBlock + threadIdx.x; c < A.n; c += (long)gridDim.x * kBlock)
-    acc += A.region[c] == 1 ? (double)A.phi[c] : 0.0;
-  const double t = block_sum(acc, red);
-  if (threadIdx.x == 0) A.partial[blockIdx.x] = t;
-}
-
-// phi' = phi - alpha_h g / max|g| - alpha_v dJ_v/dphi - alpha_1 dJ_1/dphi (every
-// phase from the old design), with dJ_v/dphi = 2 (h^d sum phi - V N h^d) h^d and
-// dJ_1/dphi = 2 (sum_m phi_m - 1) h^d.
-template <typename T>
-__global__ __launch_bounds__(kBlock) void penalty_kernel(PhaseArgs<T> A) {
-  const double gmax = A.scal[0];
-  const double hd = A.ndim == 3 ? A.h * A.h * A.h : A.h * A.h;
-  const double vpen = A.alpha_v * (2.0 * (hd * A.scal[6] - A.vol_frac * (double)A.n * hd) * hd);
+  const int m = blockIdx.y;
+  const T* g = A.g + (long)m * A.pstride;
+  const T* phi = A.phi + (long)m * A.pstride;
+  const bool rsum = A.alpha_b != 0.0 && A.region != nullptr;
+  double gm = 0.0, s = 0.0, r = 0.0;
   for (long c = (long)blockIdx.x * kBlock + threadIdx.x; c < A.n; c += (long)gridDim.x * kBlock) {
-    const double f = (double)A.phi[c];
-    const double gh = gmax > 0.0 ? (double)A.g[c] / gmax : 0.0;
-    double y = (f - A.alpha * gh) - vpen;
-    if (A.alpha_1 != 0.0) {
-      const double tot = A.total != nullptr ? A.total[c] : f;
-      y = y - A.alpha_1 * (2.0 * (tot - 1.0) * hd);
-    }
-    if (A.alpha_b != 0.0 && A.region != nullptr && A.region[c] == 1) y = y - A.alpha_b * (2.0 * (hd * A.scal[7]) * hd);
-    A.work[c] = y;
+    gm = fmax(gm, fabs((double)g[c]));
+    const double f = (double)phi[c];
+    s += f;
+    if (rsum) r += A.region[c] == 1 ? f : 0.0;
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) A.scal[3] = -vpen;
+  gm = block_max(gm, red);
+  s = block_sum(s, red);
+  if (rsum) r = block_sum(r, red);
+  if (threadIdx.x == 0) {
+    double* q = A.partial + 3 * ((long)m * gridDim.x + blockIdx.x);
+    q[0] = gm;
+    q[1] = s;
+    q[2] = r;
+  }
+}
+
+// Per phase (one wave each): the three totals and the volume-penalty term
+// alpha_v dJ_v/dphi = alpha_v 2 (h^d sum phi - V N h^d) h^d.
+template <typename T>
+__global__ void pen_final_kernel(PenaltyArgs<T> A) {
+  const int m = blockIdx.x;
+  const int nb = A.nblocks;
+  const double* q = A.partial + 3L * m * nb;
+  double gm = 0.0, s = 0.0, r = 0.0;
+  for (int b = threadIdx.x; b < nb; b += kWave) {
+    gm = fmax(gm, q[3 * b]);
+    s += q[3 * b + 1];
+    r += q[3 * b + 2];
+  }
+  gm = wave_max(gm);
+  s = wave_sum(s);
+  r = wave_sum(r);
+  if (threadIdx.x == 0) {
+    double* sc = A.scal + 8 * m;
+    const double hd = A.ndim == 3 ? A.h * A.h * A.h : A.h * A.h;
+    const double vpen = A.alpha_v * (2.0 * (hd * s - A.vol_frac[m] * (double)A.n * hd) * hd);
+    sc[0] = gm;
+    sc[1] = vpen;
+    sc[3] = -vpen;
+    sc[6] = s;
+    sc[7] = r;
+  }
+}
+
+// phi'_m at cell c: phi - alpha_h g / max|g| - alpha_v dJ_v/dphi - alpha_1 dJ_1/dphi
+// - alpha_b dJ_b/dphi, with dJ_1/dphi = 2 (sum_m phi_m - 1) h^d (tot: that sum at c)
+// and dJ_b/dphi = 2 h^d (sum over the void region) h^d on the region's cells.
+template <typename T>
+__device__ inline double pen_value(const PenaltyArgs<T>& A, int m, long c, double tot, double hd) {
+  const double* sc = A.scal + 8 * m;
+  const double gmax = sc[0];
+  const double f = (double)A.phi[(long)m * A.pstride + c];
+  const double gh = gmax > 0.0 ? (double)A.g[(long)m * A.pstride + c] / gmax : 0.0;
+  double y = (f - A.alpha * gh) - sc[1];
+  if (A.alpha_1 != 0.0) y = y - A.alpha_1 * (2.0 * (tot - 1.0) * hd);
+  if (A.alpha_b != 0.0 && A.region != nullptr && A.region[c] == 1) y = y - A.alpha_b * (2.0 * (hd * sc[7]) * hd);
+  return y;
+}
+
+// sum over the stored phases at cell c (only needed by the partition term)
+template <typename T>
+__device__ inline double phase_total(const PenaltyArgs<T>& A, long c) {
+  if (A.alpha_1 == 0.0) return 0.0;
+  double t = 0.0;
+  for (int m = 0; m < A.nphase; ++m) t += (double)A.phi[(long)m * A.pstride + c];
+  return t;
 }
 
 // Mirror-boundary Laplacian of a double field at cell (i, j, k).
@@ -269,61 +300,84 @@ __device__ inline double lap_mirror(const double* x, long c, int i, int j, int k
   return lap * rh2;
 }
 
-// mu = w'(phi') - gamma lap(phi'), w = sin^2(pi phi) / 64 (Eq. 2.15)
+// mu_m = w'(phi'_m) - gamma lap(phi'_m), w = sin^2(pi phi) / 64 (Eq. 2.15), phi'
+// formed on the fly at the cell and its (mirrored) neighbours
 template <typename T>
-__global__ __launch_bounds__(kBlock) void mu_kernel(PhaseArgs<T> A) {
+__global__ __launch_bounds__(kBlock) void pen_mu_kernel(PenaltyArgs<T> A) {
   const double rh2 = 1.0 / (A.h * A.h);
+  const double hd = A.ndim == 3 ? A.h * A.h * A.h : A.h * A.h;
   const double kPi = 3.141592653589793;
   const long sxy = (long)A.nx * A.ny;
   for (long c = (long)blockIdx.x * kBlock + threadIdx.x; c < A.n; c += (long)gridDim.x * kBlock) {
     const int k = (int)(c / sxy);
     const long rem = c - (long)k * sxy;
     const int j = (int)(rem / A.nx), i = (int)(rem - (long)j * A.nx);
-    const double x = A.work[c];
-    const double wp = (kPi / 64.0) * sin(2.0 * kPi * x);
-    A.work2[c] = wp - A.gamma * lap_mirror(A.work, c, i, j, k, A.nx, A.ny, A.nz, A.ndim, sxy, rh2);
+    // neighbours (a missing one is the cell itself)
+    long nb[6] = {i > 0 ? c - 1 : c,  i < A.nx - 1 ? c + 1 : c, j > 0 ? c - A.nx : c,
+                  j < A.ny - 1 ? c + A.nx : c, k > 0 ? c - sxy : c, k < A.nz - 1 ? c + sxy : c};
+    const int nn = A.ndim == 3 ? 6 : 4;
+    double tc = phase_total(A, c), tn[6];
+    for (int q = 0; q < nn; ++q) tn[q] = phase_total(A, nb[q]);
+    for (int m = 0; m < A.nphase; ++m) {
+      const double v = pen_value(A, m, c, tc, hd);
+      double x[6];
+      for (int q = 0; q < nn; ++q) x[q] = nb[q] == c ? v : pen_value(A, m, nb[q], tn[q], hd);
+      double lap = (x[0] + x[1] - 2.0 * v) + (x[2] + x[3] - 2.0 * v);
+      if (A.ndim == 3) lap += x[4] + x[5] - 2.0 * v;
+      lap *= rh2;
+      const double wp = (kPi / 64.0) * sin(2.0 * kPi * v);
+      A.mu[(long)m * A.mstride + c] = wp - A.gamma * lap;
+    }
   }
 }
 
-// phi = phi' + dt_ch D lap(mu); the new sum of the phase into the block partials
+// phi_m = phi'_m + dt_ch D lap(mu_m) (passive-solid cells reset: phase 0 to 1, the
+// others to 0), in place (a thread reads only its own cell's old fractions);
+// each phase's new sum into the block partials
 template <typename T>
-__global__ __launch_bounds__(kBlock) void ch_kernel(PhaseArgs<T> A) {
+__global__ __launch_bounds__(kBlock) void pen_ch_kernel(PenaltyArgs<T> A) {
   __shared__ double red[kBlock / kWave];
   const double rh2 = 1.0 / (A.h * A.h);
+  const double hd = A.ndim == 3 ? A.h * A.h * A.h : A.h * A.h;
   const long sxy = (long)A.nx * A.ny;
   const double step = A.dt_ch * A.mobility;
-  double acc = 0.0;
+  double acc[kMaxPhase];
+  for (int m = 0; m < kMaxPhase; ++m) acc[m] = 0.0;
   for (long c = (long)blockIdx.x * kBlock + threadIdx.x; c < A.n; c += (long)gridDim.x * kBlock) {
     const int k = (int)(c / sxy);
     const long rem = c - (long)k * sxy;
     const int j = (int)(rem / A.nx), i = (int)(rem - (long)j * A.nx);
-    double y = A.work[c] + step * lap_mirror(A.work2, c, i, j, k, A.nx, A.ny, A.nz, A.ndim, sxy, rh2);
-    if (A.region != nullptr && A.region[c] == 2) y = A.first ? 1.0 : 0.0;   // passive solid
-    const T t = (T)y;
-    A.phi[c] = t;
-    acc += (double)t;
+    const double tc = phase_total(A, c);
+    const bool passive = A.region != nullptr && A.region[c] == 2;
+    double y[kMaxPhase];
+    for (int m = 0; m < A.nphase; ++m) {
+      y[m] = pen_value(A, m, c, tc, hd) +
+             step * lap_mirror(A.mu + (long)m * A.mstride, c, i, j, k, A.nx, A.ny, A.nz, A.ndim, sxy, rh2);
+      if (passive) y[m] = m == 0 ? 1.0 : 0.0;
+    }
+    for (int m = 0; m < A.nphase; ++m) {
+      const T t = (T)y[m];
+      A.phi[(long)m * A.pstride + c] = t;
+      acc[m] += (double)t;
+    }
   }
-  const double tot = block_sum(acc, red);
-  if (threadIdx.x == 0) A.partial[blockIdx.x] = tot;
+  for (int m = 0; m < A.nphase; ++m) {
+    const double tot = block_sum(acc[m], red);
+    if (threadIdx.x == 0) A.partial[(long)m * gridDim.x + blockIdx.x] = tot;
+  }
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void total_kernel(const T* phi, long ncell, int nphase, long n, double* total) {
-  for (long c = (long)blockIdx.x * kBlock + threadIdx.x; c < n; c += (long)gridDim.x * kBlock) {
-    double t = 0.0;
-    for (int m = 0; m < nphase; ++m) t += (double)phi[c + m * ncell];
-    total[c] = t;
-  }
+__global__ void pen_volume_kernel(PenaltyArgs<T> A) {
+  const int m = blockIdx.x;
+  const double* q = A.partial + (long)m * A.nblocks;
+  double s = 0.0;
+  for (int b = threadIdx.x; b < A.nblocks; b += kWave) s += q[b];
+  s = wave_sum(s);
+  if (threadIdx.x == 0) A.scal[8 * m + 4] = s / (double)A.n;
 }
 
 }  // namespace
-
-template <typename T>
-void launch_phase_total(const T* phi, long ncell, int nphase, long n, double* total, hipStream_t s) {
-  hipLaunchKernelGGL((total_kernel<T>), dim3(phase_blocks(n)), dim3(kBlock), 0, s, phi, ncell, nphase, n, total);
-}
-template void launch_phase_total<float>(const float*, long, int, long, double*, hipStream_t);
-template void launch_phase_total<double>(const double*, long, int, long, double*, hipStream_t);
 
 int phase_blocks(long n) {
   long b = (n + kBlock - 1) / kBlock;
@@ -357,35 +411,16 @@ void launch_phase_apply(const PhaseArgs<T>& a, hipStream_t s) {
 }
 
 template <typename T>
-void launch_penalty_prep(const PhaseArgs<T>& a, hipStream_t s) {
-  launch_phase_gmax<T>(a, s);
-  hipLaunchKernelGGL((sum_kernel<T>), dim3(a.nblocks), dim3(kBlock), 0, s, a);
-  hipLaunchKernelGGL(sum_final_kernel, dim3(1), dim3(kWave), 0, s, a.partial, a.nblocks, a.scal, 6);
-  if (a.alpha_b != 0.0 && a.region != nullptr) {
-    hipLaunchKernelGGL((region_sum_kernel<T>), dim3(a.nblocks), dim3(kBlock), 0, s, a);
-    hipLaunchKernelGGL(sum_final_kernel, dim3(1), dim3(kWave), 0, s, a.partial, a.nblocks, a.scal, 7);
-  }
+void launch_penalty_update(const PenaltyArgs<T>& a, hipStream_t s) {
+  hipLaunchKernelGGL((pen_reduce_kernel<T>), dim3(a.nblocks, a.nphase), dim3(kBlock), 0, s, a);
+  hipLaunchKernelGGL((pen_final_kernel<T>), dim3(a.nphase), dim3(kWave), 0, s, a);
+  hipLaunchKernelGGL((pen_mu_kernel<T>), dim3(a.nblocks), dim3(kBlock), 0, s, a);
+  hipLaunchKernelGGL((pen_ch_kernel<T>), dim3(a.nblocks), dim3(kBlock), 0, s, a);
+  hipLaunchKernelGGL((pen_volume_kernel<T>), dim3(a.nphase), dim3(kWave), 0, s, a);
 }
 
-template <typename T>
-void launch_penalty_step(const PhaseArgs<T>& a, hipStream_t s) {
-  hipLaunchKernelGGL((penalty_kernel<T>), dim3(a.nblocks), dim3(kBlock), 0, s, a);
-}
-
-template <typename T>
-void launch_cahn_hilliard(const PhaseArgs<T>& a, hipStream_t s) {
-  hipLaunchKernelGGL((mu_kernel<T>), dim3(a.nblocks), dim3(kBlock), 0, s, a);
-  hipLaunchKernelGGL((ch_kernel<T>), dim3(a.nblocks), dim3(kBlock), 0, s, a);
-  hipLaunchKernelGGL(volume_final_kernel, dim3(1), dim3(kWave), 0, s, a.partial, a.nblocks, a.scal,
-                     (double)a.n);
-}
-
-template void launch_penalty_prep<float>(const PhaseArgs<float>&, hipStream_t);
-template void launch_penalty_prep<double>(const PhaseArgs<double>&, hipStream_t);
-template void launch_penalty_step<float>(const PhaseArgs<float>&, hipStream_t);
-template void launch_penalty_step<double>(const PhaseArgs<double>&, hipStream_t);
-template void launch_cahn_hilliard<float>(const PhaseArgs<float>&, hipStream_t);
-template void launch_cahn_hilliard<double>(const PhaseArgs<double>&, hipStream_t);
+template void launch_penalty_update<float>(const PenaltyArgs<float>&, hipStream_t);
+template void launch_penalty_update<double>(const PenaltyArgs<double>&, hipStream_t);
 template void launch_phase_gmax<float>(const PhaseArgs<float>&, hipStream_t);
 template void launch_phase_gmax<double>(const PhaseArgs<double>&, hipStream_t);
 template void launch_phase_step<float>(const PhaseArgs<float>&, hipStream_t);

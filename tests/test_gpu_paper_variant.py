@@ -153,3 +153,37 @@ def test_hybrid_schedule_heat_parity():
     assert info[0]["iters"] == iters == 100
     assert rel_l2(host(u, prob.cell_shape()), want) < 1e-12
     ctx.close()
+
+
+@pytest.mark.parametrize("name,make", [("cant2d", lambda: W.cantilever2d(64, 32)),
+                                       ("mbb2d", lambda: W.mbb2d(48, 16))])
+def test_detached_steps_match_reported_steps(name, make):
+    """Fixed-count loops called without records are only enqueued; five of them in
+    a row give bit-identical designs, states and compliance to five reported ones."""
+    require_gpu()
+    prob = make()
+    announce(f"detached paper-schedule steps {name}")
+    ctx = context(prob, "fp32")
+    params = pv.PenaltyParams()
+    hd = prob.h ** prob.ndim
+    if prob.nphase > 1:
+        params = pv.PenaltyParams(alpha_v=0.25 / (prob.ncell * hd * hd))
+    out = []
+    for info in (True, False):
+        phi = dev(W.initial_phi(prob), torch.float32)
+        u = ctx.new_state()
+        v = ctx.new_state()
+        g = ctx.new_cells()
+        comp = torch.zeros(2, dtype=torch.float64, device="cuda")
+        for _ in range(5):
+            st, si, pi, _ = ctx.step(phi, u, v, g, vol_frac=prob.vol_frac, compliance=comp,
+                                     apt=dict(theta=1.0, replay_iters=20, check_every=20, n_pt=20),
+                                     phase=_penalty_kw(params), info=info)
+            assert (si is None) == (not info)
+        torch.cuda.synchronize()
+        out.append((phi.clone(), u.clone(), comp.clone()))
+    assert torch.equal(out[0][0], out[1][0])
+    assert torch.equal(out[0][1], out[1][1])
+    assert torch.equal(out[0][2], out[1][2])
+    assert torch.isfinite(out[1][0]).all()
+    ctx.close()
