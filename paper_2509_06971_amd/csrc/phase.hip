@@ -120,26 +120,36 @@ __global__ void bracket_init_kernel(const double* partial, int nb, double* scal,
   }
 }
 
+// The candidates go in chunks of kChunk (a thread's sums of one chunk stay in
+// registers; the cells are read once per chunk), each sum in the same order as
+// with all candidates at once.
+constexpr int kChunk = 16;
+
 template <typename T>
 __global__ __launch_bounds__(kBlock) void pass_kernel(PhaseArgs<T> A) {
   __shared__ double sh[kBlock / kWave][kCand + 1];
   const double lo = A.scal[1], hi = A.scal[2];
   const double step = (hi - lo) / (kCand + 1);
-  double acc[kCand];
-#pragma unroll
-  for (int k = 0; k < kCand; ++k) acc[k] = 0.0;
-  for (long c = (long)blockIdx.x * kBlock + threadIdx.x; c < A.n; c += (long)gridDim.x * kBlock) {
-    const double x = A.work[c];
-    double lb, ub;
-    cell_bounds(A, c, lb, ub);
-#pragma unroll
-    for (int k = 0; k < kCand; ++k) acc[k] += fmin(fmax(x + (lo + (k + 1) * step), lb), ub);
-  }
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+  for (int k0 = 0; k0 < kCand; k0 += kChunk) {
+    double acc[kChunk];
 #pragma unroll
-  for (int k = 0; k < kCand; ++k) {
-    const double s = wave_sum(acc[k]);
-    if (lane == 0) sh[w][k] = s;
+    for (int q = 0; q < kChunk; ++q) acc[q] = 0.0;
+    for (long c = (long)blockIdx.x * kBlock + threadIdx.x; c < A.n; c += (long)gridDim.x * kBlock) {
+      const double x = A.work[c];
+      double lb, ub;
+      cell_bounds(A, c, lb, ub);
+#pragma unroll
+      for (int q = 0; q < kChunk; ++q) {
+        const int k = k0 + q;
+        if (k < kCand) acc[q] += fmin(fmax(x + (lo + (k + 1) * step), lb), ub);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < kChunk; ++q) {
+      const double s = wave_sum(acc[q]);
+      if (lane == 0 && k0 + q < kCand) sh[w][k0 + q] = s;
+    }
   }
   __syncthreads();
   if (threadIdx.x < kCand) {
@@ -155,7 +165,9 @@ __global__ void bracket_kernel(const double* partial, int nb, double* scal) {
   __shared__ double V[kCand];
   const int k = threadIdx.x;
   if (k < kCand) {
+    // (unrolled so that many loads are in flight; the additions keep their order)
     double s = 0.0;
+#pragma unroll 16
     for (int b = 0; b < nb; ++b) s += partial[(long)b * (kCand + 1) + k];
     V[k] = s;
   }
