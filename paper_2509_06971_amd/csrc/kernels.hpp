@@ -220,13 +220,14 @@ template <typename T> void launch_phase_apply(const PhaseArgs<T>& a, hipStream_t
 int phase_blocks(long n);
 
 // The paper's penalty update and Cahn-Hilliard step for every stored phase of
-// one design, in five launches whatever the phase count.
+// one design, in six launches whatever the phase count.
 template <typename T>
 struct PenaltyArgs {
   T* phi;                   // phase 0 of the design (in/out); phase m at + m * pstride
   const T* g;               // sensitivity, same layout
   long pstride;             // elements between phases (the context's cell count)
   int nphase;
+  double* p1;               // phi' of phase m at + m * mstride (double)
   double* mu;               // chemical potential of phase m at + m * mstride (double)
   long mstride;
   double* partial;          // per block scratch, >= 3 * nphase * nblocks

@@ -868,9 +868,9 @@ petto_status phase_update_impl(petto_ctx* c, void* phi, const void* grad, const 
   const T* g = static_cast<const T*>(grad);
   const int passes = pp->bisect_passes > 0 ? pp->bisect_passes : 9;
   if (pp->model == PETTO_UPDATE_PENALTY_CH) {
-    // every stored phase of a design per launch: totals, phi' formed on the fly,
-    // mu per phase into the work buffer, then the Cahn-Hilliard step in place
-    if (c->pen_work == nullptr) PETTO_TRY(dalloc_t(c, &c->pen_work, (size_t)c->nphase * c->max_cells));
+    // every stored phase of a design per launch: totals, phi' and mu per phase into
+    // the work buffer, then the Cahn-Hilliard step in place
+    if (c->pen_work == nullptr) PETTO_TRY(dalloc_t(c, &c->pen_work, (size_t)2 * c->nphase * c->max_cells));
     for (int d = 0; d < c->nprob; ++d) {
       const CellRange& R = c->h_ranges[d];
       const double h = R.h;
@@ -879,7 +879,8 @@ petto_status phase_update_impl(petto_ctx* c, void* phi, const void* grad, const 
       a.g = g + R.off;
       a.pstride = c->ncell;
       a.nphase = c->nphase;
-      a.mu = c->pen_work;
+      a.p1 = c->pen_work;
+      a.mu = c->pen_work + (long)c->nphase * c->max_cells;
       a.mstride = c->max_cells;
       a.partial = c->phase_partial;
       a.scal = c->phase_scal + (long)kMaxPhase * d * 8;

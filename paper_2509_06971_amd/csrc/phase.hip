@@ -295,6 +295,16 @@ __device__ inline double phase_total(const PenaltyArgs<T>& A, long c) {
   return t;
 }
 
+// phi'_m of every phase at every cell
+template <typename T>
+__global__ __launch_bounds__(kBlock) void pen_p1_kernel(PenaltyArgs<T> A) {
+  const double hd = A.ndim == 3 ? A.h * A.h * A.h : A.h * A.h;
+  for (long c = (long)blockIdx.x * kBlock + threadIdx.x; c < A.n; c += (long)gridDim.x * kBlock) {
+    const double tot = phase_total(A, c);
+    for (int m = 0; m < A.nphase; ++m) A.p1[(long)m * A.mstride + c] = pen_value(A, m, c, tot, hd);
+  }
+}
+
 // Mirror-boundary Laplacian of a double field at cell (i, j, k).
 __device__ inline double lap_mirror(const double* x, long c, int i, int j, int k, int nx, int ny, int nz, int ndim,
                                     long sxy, double rh2) {
@@ -312,45 +322,31 @@ __device__ inline double lap_mirror(const double* x, long c, int i, int j, int k
   return lap * rh2;
 }
 
-// mu_m = w'(phi'_m) - gamma lap(phi'_m), w = sin^2(pi phi) / 64 (Eq. 2.15), phi'
-// formed on the fly at the cell and its (mirrored) neighbours
+// mu_m = w'(phi'_m) - gamma lap(phi'_m), w = sin^2(pi phi) / 64 (Eq. 2.15)
 template <typename T>
 __global__ __launch_bounds__(kBlock) void pen_mu_kernel(PenaltyArgs<T> A) {
   const double rh2 = 1.0 / (A.h * A.h);
-  const double hd = A.ndim == 3 ? A.h * A.h * A.h : A.h * A.h;
   const double kPi = 3.141592653589793;
   const long sxy = (long)A.nx * A.ny;
   for (long c = (long)blockIdx.x * kBlock + threadIdx.x; c < A.n; c += (long)gridDim.x * kBlock) {
     const int k = (int)(c / sxy);
     const long rem = c - (long)k * sxy;
     const int j = (int)(rem / A.nx), i = (int)(rem - (long)j * A.nx);
-    // neighbours (a missing one is the cell itself)
-    long nb[6] = {i > 0 ? c - 1 : c,  i < A.nx - 1 ? c + 1 : c, j > 0 ? c - A.nx : c,
-                  j < A.ny - 1 ? c + A.nx : c, k > 0 ? c - sxy : c, k < A.nz - 1 ? c + sxy : c};
-    const int nn = A.ndim == 3 ? 6 : 4;
-    double tc = phase_total(A, c), tn[6];
-    for (int q = 0; q < nn; ++q) tn[q] = phase_total(A, nb[q]);
     for (int m = 0; m < A.nphase; ++m) {
-      const double v = pen_value(A, m, c, tc, hd);
-      double x[6];
-      for (int q = 0; q < nn; ++q) x[q] = nb[q] == c ? v : pen_value(A, m, nb[q], tn[q], hd);
-      double lap = (x[0] + x[1] - 2.0 * v) + (x[2] + x[3] - 2.0 * v);
-      if (A.ndim == 3) lap += x[4] + x[5] - 2.0 * v;
-      lap *= rh2;
+      const double* x = A.p1 + (long)m * A.mstride;
+      const double v = x[c];
       const double wp = (kPi / 64.0) * sin(2.0 * kPi * v);
-      A.mu[(long)m * A.mstride + c] = wp - A.gamma * lap;
+      A.mu[(long)m * A.mstride + c] = wp - A.gamma * lap_mirror(x, c, i, j, k, A.nx, A.ny, A.nz, A.ndim, sxy, rh2);
     }
   }
 }
 
 // phi_m = phi'_m + dt_ch D lap(mu_m) (passive-solid cells reset: phase 0 to 1, the
-// others to 0), in place (a thread reads only its own cell's old fractions);
-// each phase's new sum into the block partials
+// others to 0); each phase's new sum into the block partials
 template <typename T>
 __global__ __launch_bounds__(kBlock) void pen_ch_kernel(PenaltyArgs<T> A) {
   __shared__ double red[kBlock / kWave];
   const double rh2 = 1.0 / (A.h * A.h);
-  const double hd = A.ndim == 3 ? A.h * A.h * A.h : A.h * A.h;
   const long sxy = (long)A.nx * A.ny;
   const double step = A.dt_ch * A.mobility;
   double acc[kMaxPhase];
@@ -359,16 +355,12 @@ __global__ __launch_bounds__(kBlock) void pen_ch_kernel(PenaltyArgs<T> A) {
     const int k = (int)(c / sxy);
     const long rem = c - (long)k * sxy;
     const int j = (int)(rem / A.nx), i = (int)(rem - (long)j * A.nx);
-    const double tc = phase_total(A, c);
     const bool passive = A.region != nullptr && A.region[c] == 2;
-    double y[kMaxPhase];
     for (int m = 0; m < A.nphase; ++m) {
-      y[m] = pen_value(A, m, c, tc, hd) +
-             step * lap_mirror(A.mu + (long)m * A.mstride, c, i, j, k, A.nx, A.ny, A.nz, A.ndim, sxy, rh2);
-      if (passive) y[m] = m == 0 ? 1.0 : 0.0;
-    }
-    for (int m = 0; m < A.nphase; ++m) {
-      const T t = (T)y[m];
+      double y = A.p1[(long)m * A.mstride + c] +
+                 step * lap_mirror(A.mu + (long)m * A.mstride, c, i, j, k, A.nx, A.ny, A.nz, A.ndim, sxy, rh2);
+      if (passive) y = m == 0 ? 1.0 : 0.0;
+      const T t = (T)y;
       A.phi[(long)m * A.pstride + c] = t;
       acc[m] += (double)t;
     }
@@ -426,6 +418,7 @@ template <typename T>
 void launch_penalty_update(const PenaltyArgs<T>& a, hipStream_t s) {
   hipLaunchKernelGGL((pen_reduce_kernel<T>), dim3(a.nblocks, a.nphase), dim3(kBlock), 0, s, a);
   hipLaunchKernelGGL((pen_final_kernel<T>), dim3(a.nphase), dim3(kWave), 0, s, a);
+  hipLaunchKernelGGL((pen_p1_kernel<T>), dim3(a.nblocks), dim3(kBlock), 0, s, a);
   hipLaunchKernelGGL((pen_mu_kernel<T>), dim3(a.nblocks), dim3(kBlock), 0, s, a);
   hipLaunchKernelGGL((pen_ch_kernel<T>), dim3(a.nblocks), dim3(kBlock), 0, s, a);
   hipLaunchKernelGGL((pen_volume_kernel<T>), dim3(a.nphase), dim3(kWave), 0, s, a);
