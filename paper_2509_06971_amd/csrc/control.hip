@@ -89,6 +89,8 @@ __global__ __launch_bounds__(kBlock) void finalize_kernel(FinalizeArgs A) {
     const int t0 = A.tile0 ? A.tile0[d] : 0;
     const int t1 = A.tile0 ? A.tile0[d + 1] : A.ntile;
     double acc = 0.0;
+    // (unrolled so that the loads overlap; the additions keep their order)
+#pragma unroll 8
     for (int t = t0 + lane; t < t1; t += kWave) acc += A.partial[t];
     acc = wave_sum(acc);
     if (lane == 0) {
@@ -120,6 +122,7 @@ __global__ __launch_bounds__(kBlock) void finalize_kernel(FinalizeArgs A) {
         // critical damping of the mode of the state at this block boundary
         double uu = 0.0, uf = 0.0, ur = 0.0;
         const double* q = A.prq + (long)d * A.rq_blocks * 3;
+#pragma unroll 8
         for (int b = 0; b < A.rq_blocks; ++b) {
           uu += q[3 * b];
           uf += q[3 * b + 1];
@@ -168,6 +171,7 @@ __global__ __launch_bounds__(kBlock) void dot_finalize_kernel(const double* pfu,
     const int t0 = tile0 ? tile0[d] : 0;
     const int t1 = tile0 ? tile0[d + 1] : ntile;
     double a = 0.0, b = 0.0;
+#pragma unroll 8
     for (int t = t0 + lane; t < t1; t += kWave) {
       a += pfu[t];
       b += pen[t];

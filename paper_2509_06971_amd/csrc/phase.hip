@@ -29,6 +29,7 @@ __global__ __launch_bounds__(kBlock) void gmax_kernel(PhaseArgs<T> A) {
 
 __global__ void gmax_final_kernel(const double* partial, int nb, double* scal) {
   double m = 0.0;
+  #pragma unroll 8
   for (int b = threadIdx.x; b < nb; b += kWave) m = fmax(m, partial[b]);
   m = wave_max(m);
   if (threadIdx.x == 0) scal[0] = m;
@@ -105,6 +106,7 @@ __global__ __launch_bounds__(kBlock) void step_kernel(PhaseArgs<T> A) {
 // Initial bracket [-max phi'', max ub - min phi''].
 __global__ void bracket_init_kernel(const double* partial, int nb, double* scal, double target) {
   double mn = INFINITY, mx = -INFINITY, ub = -INFINITY;
+  #pragma unroll 8
   for (int b = threadIdx.x; b < nb; b += kWave) {
     mn = fmin(mn, partial[3 * b]);
     mx = fmax(mx, partial[3 * b + 1]);
@@ -206,6 +208,7 @@ __global__ __launch_bounds__(kBlock) void apply_kernel(PhaseArgs<T> A) {
 
 __global__ void volume_final_kernel(const double* partial, int nb, double* scal, double n) {
   double s = 0.0;
+  #pragma unroll 8
   for (int b = threadIdx.x; b < nb; b += kWave) s += partial[b];
   s = wave_sum(s);
   if (threadIdx.x == 0) scal[4] = s / n;
@@ -251,6 +254,7 @@ __global__ void pen_final_kernel(PenaltyArgs<T> A) {
   const int nb = A.nblocks;
   const double* q = A.partial + 3L * m * nb;
   double gm = 0.0, s = 0.0, r = 0.0;
+  #pragma unroll 8
   for (int b = threadIdx.x; b < nb; b += kWave) {
     gm = fmax(gm, q[3 * b]);
     s += q[3 * b + 1];
@@ -376,6 +380,7 @@ __global__ void pen_volume_kernel(PenaltyArgs<T> A) {
   const int m = blockIdx.x;
   const double* q = A.partial + (long)m * A.nblocks;
   double s = 0.0;
+  #pragma unroll 8
   for (int b = threadIdx.x; b < A.nblocks; b += kWave) s += q[b];
   s = wave_sum(s);
   if (threadIdx.x == 0) A.scal[8 * m + 4] = s / (double)A.n;
