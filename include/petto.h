@@ -187,7 +187,9 @@ typedef struct {
 /* Create a context for nprob designs in precision prec (PETTO_FP32 / PETTO_FP64).
  * Elastic: nprob must be 1.  Heat: any nprob >= 1 (a batch, solved in shared
  * launches).  Copies the problem data (masks, loads) to the device.  *out receives
- * the context (owned by the caller; release with petto_destroy). */
+ * the context (owned by the caller; release with petto_destroy).  3D elastic
+ * problems need (n[0]+1)(n[1]+1) < 2^29 (one xy layer of positions addressed by
+ * 32-bit byte offsets), else PETTO_ERR_UNSUPPORTED. */
 petto_status petto_create(const petto_problem *probs, int32_t nprob, int32_t prec, petto_ctx **out);
 
 /* Release a context and everything it owns.  NULL is accepted. */

@@ -205,6 +205,10 @@ petto_status validate_problem(const petto_problem& p, int idx) {
         return fail(PETTO_ERR_INVALID, "problem %d: e_phase[%d] must be >= 0", idx, m);
     if (!(p.e_phase[0] > 0.0)) return fail(PETTO_ERR_INVALID, "problem %d: e_phase[0] must be > 0", idx);
   }
+  if (p.physics == PETTO_ELASTIC && p.ndim == 3 && (long)(p.n[0] + 1) * (p.n[1] + 1) >= (1L << 29))
+    // the 3D sweep addresses within one xy layer by 32-bit byte offsets (FP64: 8 B)
+    return fail(PETTO_ERR_UNSUPPORTED, "problem %d: an xy layer of %d x %d positions is too large for the 3D sweep",
+                idx, p.n[0] + 1, p.n[1] + 1);
   if (p.physics == PETTO_ELASTIC) {
     if (!(p.nu >= 0.0 && p.nu < 0.5)) return fail(PETTO_ERR_INVALID, "problem %d: nu must be in [0, 0.5)", idx);
     for (int s = 0; s < 2 * p.ndim; ++s)

@@ -137,3 +137,19 @@ def test_missing_library_fails_loudly(tmp_path):
             L.load(str(tmp_path / "nope.so"))
         finally:
             L._lib = L._lib_saved
+
+
+def test_3d_layer_size_limit(lib):
+    """The 3D sweep addresses an xy layer by 32-bit byte offsets: larger layers are
+    refused before anything is allocated (the load is never read)."""
+    arr = (L.Problem * 1)()
+    p = arr[0]
+    p.physics, p.ndim = L.ELASTIC, 3
+    p.n[0], p.n[1], p.n[2] = 30000, 30000, 2
+    p.h, p.e0, p.emin, p.nu, p.p, p.nphase = 1.0, 1.0, 1e-9, 0.3, 3.0, 1
+    dummy = (C.c_double * 1)()
+    p.load = C.cast(dummy, C.POINTER(C.c_double))
+    h = C.c_void_p()
+    assert lib.petto_create(arr, 1, L.FP32, C.byref(h)) == L.ERR_UNSUPPORTED
+    assert not h.value
+    assert b"too large for the 3D sweep" in lib.petto_last_error()
