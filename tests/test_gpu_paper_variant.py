@@ -158,8 +158,9 @@ def test_hybrid_schedule_heat_parity():
 @pytest.mark.parametrize("name,make", [("cant2d", lambda: W.cantilever2d(64, 32)),
                                        ("mbb2d", lambda: W.mbb2d(48, 16))])
 def test_detached_steps_match_reported_steps(name, make):
-    """Fixed-count loops called without records are only enqueued; five of them in
-    a row give bit-identical designs, states and compliance to five reported ones."""
+    """Fixed-count loops called without records are only enqueued; five loops with
+    records, and five with records only on some of them (detached loops before and
+    after reported ones), give bit-identical designs, states and compliance."""
     require_gpu()
     prob = make()
     announce(f"detached paper-schedule steps {name}")
@@ -169,17 +170,19 @@ def test_detached_steps_match_reported_steps(name, make):
     if prob.nphase > 1:
         params = pv.PenaltyParams(alpha_v=0.25 / (prob.ncell * hd * hd))
     out = []
-    for info in (True, False):
+    for pattern in ((True,) * 5, (False, False, True, False, True)):
         phi = dev(W.initial_phi(prob), torch.float32)
         u = ctx.new_state()
         v = ctx.new_state()
         g = ctx.new_cells()
         comp = torch.zeros(2, dtype=torch.float64, device="cuda")
-        for _ in range(5):
+        for info in pattern:
             st, si, pi, _ = ctx.step(phi, u, v, g, vol_frac=prob.vol_frac, compliance=comp,
                                      apt=dict(theta=1.0, replay_iters=20, check_every=20, n_pt=20),
                                      phase=_penalty_kw(params), info=info)
             assert (si is None) == (not info)
+            if info:
+                assert si[0]["iters"] == 40
         torch.cuda.synchronize()
         out.append((phi.clone(), u.clone(), comp.clone()))
     assert torch.equal(out[0][0], out[1][0])
