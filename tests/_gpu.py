@@ -43,16 +43,20 @@ def context(prob, prec):
 def mixed_elastic(ndim, variant=0):
     """Ragged grid with clamped, roller and free sides and a few extra pins.
     3D variant 1 has n_x a multiple of 64 and a clamped x = n_x side (the face
-    column that the 3D tiling hands to the last x-tile)."""
+    column that the 3D tiling hands to the last x-tile); variant 2 is thinner than
+    one tile in y and z and barely over one tile in x, clamped on every side."""
     if ndim == 2:
         n = (150, 37)
         side = (W.CLAMPED, W.ROLLER, W.FREE, W.CLAMPED, 0, 0)
     elif variant == 0:
         n = (70, 9, 19)
         side = (W.CLAMPED, W.FREE, W.ROLLER, W.CLAMPED, W.CLAMPED, W.FREE)
-    else:
+    elif variant == 1:
         n = (64, 7, 11)
         side = (W.FREE, W.CLAMPED, W.CLAMPED, W.ROLLER, W.FREE, W.CLAMPED)
+    else:
+        n = (66, 3, 2)
+        side = (W.CLAMPED,) * 6
     fixed = W._side_normal_fixed(ndim, n, side)
     valid = W.dof_valid_mask(ndim, n)
     rng = np.random.default_rng(11)

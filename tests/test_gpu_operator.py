@@ -15,7 +15,7 @@ TOL_FP32 = 2e-6
 
 def _elastic_cases():
     return [("mixed2d", lambda: mixed_elastic(2)), ("mixed3d", lambda: mixed_elastic(3)),
-            ("mixed3d64", lambda: mixed_elastic(3, 1)),
+            ("mixed3d64", lambda: mixed_elastic(3, 1)), ("thin3d", lambda: mixed_elastic(3, 2)),
             ("cant2d", lambda: W.cantilever2d(64, 32)), ("cant3d", lambda: W.cantilever3d(20, 8, 6)),
             ("multi3d", lambda: W.multimaterial3d(24, 10, 8))]
 
@@ -83,7 +83,7 @@ def test_heat_batch_residual_parity(prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("name,make", _elastic_cases()[:3] + [("cant2d", lambda: W.cantilever2d(64, 32))])
+@pytest.mark.parametrize("name,make", _elastic_cases()[:4] + [("cant2d", lambda: W.cantilever2d(64, 32))])
 def test_sweeps_parity(name, make, prec):
     """200 damped-wave sweeps from a random state equal the oracle's sweeps (3D:
     with both sweep tilings)."""
