@@ -245,8 +245,10 @@ petto_status petto_step(petto_ctx *ctx, void *phi, void *u, void *v, void *grad_
                         petto_solve_info *sinfo, petto_phase_info *pinfo);
 
 /* Mean duration in milliseconds of the sweep kernels of the last petto_apt_solve
- * (timed with HIP events on the solve stream around whole sweep blocks), and the
- * number of sweeps those blocks held.  Returns 0 when nothing was timed. */
+ * (timed with HIP events on the solve stream around whole launches of sweep
+ * blocks, two blocks per launch when graphs are used), and the number of sweeps
+ * those blocks held (for a solve stopped by tol, counting the blocks of its last
+ * launch).  Returns 0 when nothing was timed. */
 double petto_last_sweep_ms(const petto_ctx *ctx, int64_t *sweeps);
 
 /* Enable (1) or disable (0) the sweep timing above (off by default). */

@@ -93,6 +93,22 @@ __global__ __launch_bounds__(kBlock) void finalize_kernel(FinalizeArgs A) {
 #pragma unroll 8
     for (int t = t0 + lane; t < t1; t += kWave) acc += A.partial[t];
     acc = wave_sum(acc);
+    // the Rayleigh-quotient sums of adaptive damping, over the whole wave in a
+    // fixed order (used below only when the design goes on)
+    double uu = 0.0, uf = 0.0, ur = 0.0;
+    const bool rq = s.adapt && A.prq != nullptr;
+    if (rq) {
+      const double* q = A.prq + (long)d * A.rq_blocks * 3;
+#pragma unroll 4
+      for (int b = lane; b < A.rq_blocks; b += kWave) {
+        uu += q[3 * b];
+        uf += q[3 * b + 1];
+        ur += q[3 * b + 2];
+      }
+      uu = wave_sum(uu);
+      uf = wave_sum(uf);
+      ur = wave_sum(ur);
+    }
     if (lane == 0) {
       const double rho = sqrt(acc) / s.fnorm;
       s.sumsq = acc;
@@ -118,16 +134,8 @@ __global__ __launch_bounds__(kBlock) void finalize_kernel(FinalizeArgs A) {
       } else if (A.mode == 1) {
         s.iters += s.check_every;   // the sweeps of this block will run
       }
-      if (!s.done && s.adapt && A.prq != nullptr) {
+      if (!s.done && rq) {
         // critical damping of the mode of the state at this block boundary
-        double uu = 0.0, uf = 0.0, ur = 0.0;
-        const double* q = A.prq + (long)d * A.rq_blocks * 3;
-#pragma unroll 8
-        for (int b = 0; b < A.rq_blocks; ++b) {
-          uu += q[3 * b];
-          uf += q[3 * b + 1];
-          ur += q[3 * b + 2];
-        }
         const double uku = uf - ur;
         if (uu > 0.0 && uku > 0.0) {
           const double lam = uku / (s.hd * uu);

@@ -47,7 +47,8 @@ petto_status fail(petto_status s, const char* fmt, ...) {
   } while (0)
 
 constexpr int kBpd = 256;          // material-kernel blocks per design
-constexpr int kRqBlocks = 64;      // Rayleigh-quotient blocks per design
+constexpr int kRqBlocks = 256;     // Rayleigh-quotient blocks per design
+constexpr int kGroup = 2;          // check blocks per graph launch
 constexpr int kMaxOuter = 64;      // refinement: correction solves per call
 constexpr double kDivFactor = 1e4;
 
@@ -342,47 +343,58 @@ petto_status enqueue_block(petto_ctx* c, hipStream_t stream, bool use_graph, con
   return PETTO_OK;
 }
 
-// Run blocks until the finalize kernel reports every design done.  Two blocks are
-// kept in flight; a block enqueued after the stop finds the done flags set and its
-// kernels return at once.  Blocks timed (when enabled) are those up to the stop.
-// With last == nullptr (a fixed block count whose caller wants no report) the
-// blocks are only enqueued.
+// Run blocks until the finalize kernel reports every design done.  Blocks go to
+// the GPU in groups of kGroup per graph launch (with graphs; one poll event per
+// group): the GPU idles at every launch boundary, and a group halves their
+// number.  Two groups are kept in flight; the device applies the stop rule after
+// every block, so a block enqueued after the stop finds the done flags set and its
+// kernels return at once.  Blocks timed (when enabled) are those of the groups up
+// to the stop.  With last == nullptr (a fixed block count whose caller wants no
+// report) the groups are only enqueued.
 petto_status run_blocks(petto_ctx* c, hipStream_t stream, bool use_graph, const std::vector<const void*>& key,
                         const std::function<void(hipStream_t)>& body, int sweeps_per_block, PollRecord* last,
                         long max_blocks) {
   PETTO_TRY(ensure_events(c));
+  const int G = (use_graph && max_blocks >= kGroup) ? kGroup : 1;
+  std::vector<const void*> gkey = key;
+  gkey.push_back((const void*)(long)G);
+  const std::function<void(hipStream_t)> group = [&](hipStream_t st) {
+    for (int q = 0; q < G; ++q) body(st);
+  };
+  const long ngroups = (max_blocks + G - 1) / G;
   if (last == nullptr) {
-    // a fixed count with nothing to report: enqueue every block and return; the
+    // a fixed count with nothing to report: enqueue every group and return; the
     // host neither waits nor reads the poll ring (the finalize kernels still
     // apply the stop rule on the device)
-    for (long b = 0; b < max_blocks; ++b) PETTO_TRY(enqueue_block(c, stream, use_graph, key, body));
+    for (long b = 0; b < ngroups; ++b) PETTO_TRY(enqueue_block(c, stream, use_graph, gkey, group));
     return PETTO_OK;
   }
   long launched = 0, checked = 0;
-  std::vector<float> block_ms;
   for (;;) {
-    // never more blocks than the stop rule can use (fixed counts: exactly that many)
-    while (launched - checked < 2 && launched < max_blocks) {
+    // never more groups than the stop rule can use
+    while (launched - checked < 2 && launched < ngroups) {
       if (c->timing) HIP_TRY(hipEventRecord(c->ev_beg[launched % kRing], stream));
-      PETTO_TRY(enqueue_block(c, stream, use_graph, key, body));
+      PETTO_TRY(enqueue_block(c, stream, use_graph, gkey, group));
       HIP_TRY(hipEventRecord(c->ev_end[launched % kRing], stream));
       ++launched;
     }
     HIP_TRY(hipEventSynchronize(c->ev_end[checked % kRing]));
-    volatile PollRecord* r = &c->ring_host[checked % kRing];
+    // the record of the group's last block (every finalize writes one)
+    const long seq = (checked + 1) * G - 1;
+    volatile PollRecord* r = &c->ring_host[seq % kRing];
     const PollRecord rec{r->all_done, r->any_diverged, r->any_not_converged, r->seq};
-    if (rec.seq != (int)(checked % 0x7fffffff)) {
+    if (rec.seq != (int)(seq % 0x7fffffff)) {
       (void)hipStreamSynchronize(stream);
-      return fail(PETTO_ERR_HIP, "poll ring out of step (seq %d, expected %ld)", rec.seq, checked);
+      return fail(PETTO_ERR_HIP, "poll ring out of step (seq %d, expected %ld)", rec.seq, seq);
     }
     if (c->timing) {
       float ms = 0.f;
       HIP_TRY(hipEventElapsedTime(&ms, c->ev_beg[checked % kRing], c->ev_end[checked % kRing]));
       c->timed_ms += ms;
-      c->timed_sweeps += sweeps_per_block;
+      c->timed_sweeps += (long)sweeps_per_block * G;
     }
     ++checked;
-    if (rec.all_done || checked == max_blocks) {
+    if (rec.all_done || checked == ngroups) {
       *last = rec;
       break;
     }
