@@ -246,7 +246,7 @@ petto_status petto_step(petto_ctx *ctx, void *phi, void *u, void *v, void *grad_
 
 /* Mean duration in milliseconds of the sweep kernels of the last petto_apt_solve
  * (timed with HIP events on the solve stream around whole launches of sweep
- * blocks, two blocks per launch when graphs are used), and the number of sweeps
+ * blocks, four blocks per launch when graphs are used), and the number of sweeps
  * those blocks held (for a solve stopped by tol, counting the blocks of its last
  * launch).  Returns 0 when nothing was timed. */
 double petto_last_sweep_ms(const petto_ctx *ctx, int64_t *sweeps);

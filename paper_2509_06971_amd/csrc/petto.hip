@@ -48,7 +48,7 @@ petto_status fail(petto_status s, const char* fmt, ...) {
 
 constexpr int kBpd = 256;          // material-kernel blocks per design
 constexpr int kRqBlocks = 256;     // Rayleigh-quotient blocks per design
-constexpr int kGroup = 2;          // check blocks per graph launch
+constexpr int kGroup = 4;          // check blocks per graph launch
 constexpr int kMaxOuter = 64;      // refinement: correction solves per call
 constexpr double kDivFactor = 1e4;
 
@@ -345,8 +345,7 @@ petto_status enqueue_block(petto_ctx* c, hipStream_t stream, bool use_graph, con
 
 // Run blocks until the finalize kernel reports every design done.  Blocks go to
 // the GPU in groups of kGroup per graph launch (with graphs; one poll event per
-// group): the GPU idles at every launch boundary, and a group halves their
-// number.  Two groups are kept in flight; the device applies the stop rule after
+// group): the GPU idles at every launch boundary, and groups cut their number.  Two groups are kept in flight; the device applies the stop rule after
 // every block, so a block enqueued after the stop finds the done flags set and its
 // kernels return at once.  Blocks timed (when enabled) are those of the groups up
 // to the stop.  With last == nullptr (a fixed block count whose caller wants no
