@@ -198,11 +198,6 @@ __global__ void fill_kernel(T* p, long n, T value) {
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) p[i] = value;
 }
 
-template <typename T>
-__global__ void copy_kernel(T* dst, const T* src, long n) {
-  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) dst[i] = src[i];
-}
-
 __global__ void fold_kernel(double* u, float* d, long n, const int* all_done) {
   if (*all_done) return;
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
@@ -286,11 +281,6 @@ void launch_fill(T* p, long n, T value, hipStream_t s) {
   hipLaunchKernelGGL((fill_kernel<T>), dim3(grid_for(n)), dim3(kBlock), 0, s, p, n, value);
 }
 
-template <typename T>
-void launch_copy(T* dst, const T* src, long n, hipStream_t s) {
-  hipLaunchKernelGGL((copy_kernel<T>), dim3(grid_for(n)), dim3(kBlock), 0, s, dst, src, n);
-}
-
 void launch_fold(double* u, float* d, long n, const int* all_done, hipStream_t s) {
   hipLaunchKernelGGL(fold_kernel, dim3(grid_for(n)), dim3(kBlock), 0, s, u, d, n, all_done);
 }
@@ -301,7 +291,5 @@ template void launch_material<double>(const double*, double*, double*, const Cel
                                       double, double, double, const double*, double*, int, hipStream_t);
 template void launch_fill<float>(float*, long, float, hipStream_t);
 template void launch_fill<double>(double*, long, double, hipStream_t);
-template void launch_copy<float>(float*, const float*, long, hipStream_t);
-template void launch_copy<double>(double*, const double*, long, hipStream_t);
 
 }  // namespace petto

@@ -187,8 +187,6 @@ void launch_fill(T* p, long n, T value, hipStream_t s);
 // u += d, d = 0 (refinement: fold the FP32 correction into the double state);
 // skipped once every design is done.
 void launch_fold(double* u, float* d, long n, const int* all_done, hipStream_t s);
-template <typename T>
-void launch_copy(T* dst, const T* src, long n, hipStream_t s);
 
 // ---------------------------------------------------------------- phase update
 // One phase of one design: normalised sensitivity step, Allen-Cahn step into
