@@ -218,6 +218,14 @@ int launch_el3d_adjoint(const ElGeom& g, const ElAdjoint<U, T>& a, hipStream_t s
   return nt;
 }
 
+int el3d_adjoint_tiles(const ElGeom& g) {
+  int ax, ay, az, bx, by, bz;
+  tiles3<float>(g, ax, ay, az);
+  tiles3<double>(g, bx, by, bz);
+  const int a = ax * ay * az, b = bx * by * bz;
+  return a > b ? a : b;
+}
+
 template int launch_el3d_adjoint<float, float>(const ElGeom&, const ElAdjoint<float, float>&, hipStream_t);
 template int launch_el3d_adjoint<double, float>(const ElGeom&, const ElAdjoint<double, float>&, hipStream_t);
 template int launch_el3d_adjoint<double, double>(const ElGeom&, const ElAdjoint<double, double>&, hipStream_t);

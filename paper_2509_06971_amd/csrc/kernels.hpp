@@ -47,7 +47,7 @@ int launch_el2d_tb(const ElGeom& g, const ElSweep<T>& a, hipStream_t s);
 int el2d_tb_tiles(const ElGeom& g, int K);   // 0 for an unsupported K
 int el3d_tiles_prec(const ElGeom& g, bool fp64);   // for the tiling g.tile3d
 // Tiling for a grid: the large one when it gives at least two workgroups per
-// compute unit, else the small one.
+// compute unit, else the shorter-column tiling of the smaller modelled time.
 int el3d_choose_tiling(const ElGeom& g, bool fp64, int ncu);
 
 // Sensitivity: per cell g = -dE/dphi * B(w,u)/E-free form, plus dot(F,u) and 2 Pi(u)
@@ -69,6 +69,9 @@ template <typename U, typename T>
 int launch_el2d_adjoint(const ElGeom& g, const ElAdjoint<U, T>& a, hipStream_t s);
 template <typename U, typename T>
 int launch_el3d_adjoint(const ElGeom& g, const ElAdjoint<U, T>& a, hipStream_t s);
+// workgroups of the 3D sensitivity launch (one partial-sum slot each), the larger
+// of the two state precisions
+int el3d_adjoint_tiles(const ElGeom& g);
 
 // ---------------------------------------------------------------- heat (2D batch)
 struct HeatDesign {

@@ -1053,7 +1053,9 @@ petto_status petto_create(const petto_problem* probs, int32_t nprob, int32_t pre
     }
     c->m0 = g.lam0 + 2.0 * g.mu0;
     c->h_ranges.push_back({0, c->ncell, g.nx, g.ny, g.nz, 0, p.h});
-    c->ntile = c->ndim == 2 ? el2d_tiles(g) : el3d_tiles(g);
+    // partial-sum slots: every sweep tiling, and the sensitivity launch (whose 3D
+    // tiling is its own)
+    c->ntile = c->ndim == 2 ? el2d_tiles(g) : std::max(el3d_tiles(g), el3d_adjoint_tiles(g));
     if (c->ndim == 2)
       for (int k : {2, 4, 5, 8, 10}) c->ntile = std::max(c->ntile, el2d_tb_tiles(g, k));
   } else {
@@ -1442,6 +1444,12 @@ petto_status petto_adjoint(petto_ctx* ctx, const void* phi, const void* u, const
   if (phi == nullptr || u == nullptr || grad_phi == nullptr)
     return fail(PETTO_ERR_INVALID, "phi, u and grad_phi must be non-NULL");
   hipStream_t s = static_cast<hipStream_t>(stream);
+  if (ctx->physics == PETTO_ELASTIC) {
+    const int need = ctx->ndim == 2 ? el2d_tiles(ctx->geom) : el3d_adjoint_tiles(ctx->geom);
+    if (need > ctx->ntile)
+      return fail(PETTO_ERR_UNSUPPORTED, "sensitivity launch needs %d partial-sum slots, the context holds %d",
+                  need, ctx->ntile);
+  }
   int nt = 0;
   if (ctx->prec == PETTO_FP64) nt = adjoint_launch<double, double>(ctx, phi, u, w, grad_phi, s);
   else if (state_fp64) nt = adjoint_launch<double, float>(ctx, phi, u, w, grad_phi, s);

@@ -36,6 +36,34 @@ def test_adjoint_parity(name, make, with_w):
     ctx.close()
 
 
+@pytest.mark.parametrize("name,make,prec", [("cant3d_128x64x64", lambda: W.cantilever3d(128, 64, 64), "fp64"),
+                                            ("multi3d_256x128x18", lambda: W.multimaterial3d(256, 128, 18), "fp32")])
+def test_adjoint_parity_large_3d(name, make, prec):
+    """3D grids on which the sensitivity launch has several times the workgroups
+    of any sweep tiling, so every one of its partial-sum slots must fit the
+    context's buffers: gradient and both compliance sums against the oracle."""
+    require_gpu()
+    prob = make()
+    announce(f"adjoint large {name} {prec}")
+    phi = W.random_phi(prob, 4, 0.05, 1.0)
+    u = W.random_u(prob, 5)
+    ctx = context(prob, prec)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    if prec == "fp32":
+        phi = phi.astype(np.float32).astype(np.float64)
+    g = ctx.new_cells()
+    comp = ctx.adjoint(dev(phi, dt), dev(u, torch.float64), g, state_fp64=True)
+    torch.cuda.synchronize()
+    want = design.sensitivity(u, phi, prob)
+    got = host(g, phi.shape)
+    tol = 1e-12 if prec == "fp64" else 1e-6
+    assert np.abs(got - want).max() <= tol * np.abs(want).max()
+    c = comp.cpu().numpy()
+    assert c[0] == pytest.approx(float(np.sum(design.load_vector(prob) * u)), rel=1e-12)
+    assert c[1] == pytest.approx(2.0 * design.strain_energy_total(u, phi, prob), rel=1e-12)
+    ctx.close()
+
+
 def test_heat_adjoint_parity():
     require_gpu()
     probs, phis, _ = W.heat_batch_small()
