@@ -63,10 +63,11 @@ def apt_solve(residual_fn, u0, *, dt, theta, hd, fnorm, ncell, tol=1e-6, check_e
               max_iter=10**7, n_iter=None, v0=None, div_factor=1e4, adapt=None):
     """Run sweeps from (u0, v0=0).  With n_iter given, run exactly that many sweeps
     (the stop rule is still evaluated for reporting).  adapt = (F, dt_of_theta):
-    after every checking sweep that does not stop the iteration, re-choose theta
-    with `adapted_theta` from the state that sweep produced (floor: the given
-    theta) and the step dt_of_theta(theta); the new values apply from the next
-    sweep."""
+    theta is chosen with `adapted_theta` (floor: the given theta) from the
+    starting state before the first sweep (a state of zeros has no quotient and
+    keeps the floor) and again after every checking sweep that does not stop the
+    iteration, from the state that sweep produced, with the step
+    dt_of_theta(theta); the new values apply from the next sweep."""
     theta_min = theta
     u = np.array(u0, dtype=np.float64)
     v = np.zeros_like(u) if v0 is None else np.array(v0, dtype=np.float64)
@@ -76,6 +77,10 @@ def apt_solve(residual_fn, u0, *, dt, theta, hd, fnorm, ncell, tol=1e-6, check_e
     first = None
     limit = n_iter if n_iter is not None else max_iter
     converged = diverged = False
+    if adapt is not None:
+        th = adapted_theta(u, residual_fn(u), adapt[0], hd, theta_min)
+        if th is not None:
+            theta, dt = th, adapt[1](th)
     while it < limit:
         r = residual_fn(u)
         it += 1

@@ -80,6 +80,53 @@ __global__ void setup_kernel(SetupArgs A) {
   }
 }
 
+// The three Rayleigh-quotient sums of design d, over the whole wave in a fixed
+// order (every lane returns the totals).
+__device__ __forceinline__ void rq_sums(const double* prq, int rq_blocks, int d, int lane, double& uu,
+                                        double& uf, double& ur) {
+  const double* q = prq + (long)d * rq_blocks * 3;
+  uu = uf = ur = 0.0;
+#pragma unroll 4
+  for (int b = lane; b < rq_blocks; b += kWave) {
+    uu += q[3 * b];
+    uf += q[3 * b + 1];
+    ur += q[3 * b + 2];
+  }
+  uu = wave_sum(uu);
+  uf = wave_sum(uf);
+  ur = wave_sum(ur);
+}
+
+// Critical damping of the mode of the state the sums describe: lam = u.Ku /
+// (h^d u.u) with u.Ku = u.F - u.r, theta = 1 / (4 lam) (never below the floor),
+// and the step for that theta.  A state without a positive quotient (u = 0)
+// leaves the damping as it is.
+__device__ __forceinline__ void adapt_damping(SolveState& s, double uu, double uf, double ur) {
+  const double uku = uf - ur;
+  if (uu > 0.0 && uku > 0.0) {
+    const double lam = uku / (s.hd * uu);
+    const double th = fmin(fmax(s.theta_min, 0.25 / lam), 1e6);
+    const double dt = s.dt_scale * sqrt(th);
+    s.theta = th;
+    s.dt = dt;
+    s.a = th / (th + dt);
+    s.c = dt / ((th + dt) * s.hd);
+  }
+}
+
+// Damping chosen from the starting state of a solve, before its first sweep (a
+// warm start then begins at the damping of its own mode rather than at the floor).
+__global__ __launch_bounds__(kBlock) void adapt_kernel(SolveState* st, const double* prq, int rq_blocks, int ndes) {
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+  for (int d = w; d < ndes; d += kBlock / kWave) {
+    SolveState& s = st[d];
+    if (s.done || !s.adapt) continue;
+    double uu, uf, ur;
+    rq_sums(prq, rq_blocks, d, lane, uu, uf, ur);
+    if (lane == 0) adapt_damping(s, uu, uf, ur);
+  }
+}
+
 __global__ __launch_bounds__(kBlock) void finalize_kernel(FinalizeArgs A) {
   __shared__ int sh_flags[3];
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
@@ -97,18 +144,7 @@ __global__ __launch_bounds__(kBlock) void finalize_kernel(FinalizeArgs A) {
     // fixed order (used below only when the design goes on)
     double uu = 0.0, uf = 0.0, ur = 0.0;
     const bool rq = s.adapt && A.prq != nullptr;
-    if (rq) {
-      const double* q = A.prq + (long)d * A.rq_blocks * 3;
-#pragma unroll 4
-      for (int b = lane; b < A.rq_blocks; b += kWave) {
-        uu += q[3 * b];
-        uf += q[3 * b + 1];
-        ur += q[3 * b + 2];
-      }
-      uu = wave_sum(uu);
-      uf = wave_sum(uf);
-      ur = wave_sum(ur);
-    }
+    if (rq) rq_sums(A.prq, A.rq_blocks, d, lane, uu, uf, ur);
     if (lane == 0) {
       const double rho = sqrt(acc) / s.fnorm;
       s.sumsq = acc;
@@ -134,19 +170,8 @@ __global__ __launch_bounds__(kBlock) void finalize_kernel(FinalizeArgs A) {
       } else if (A.mode == 1) {
         s.iters += s.check_every;   // the sweeps of this block will run
       }
-      if (!s.done && rq) {
-        // critical damping of the mode of the state at this block boundary
-        const double uku = uf - ur;
-        if (uu > 0.0 && uku > 0.0) {
-          const double lam = uku / (s.hd * uu);
-          const double th = fmin(fmax(s.theta_min, 0.25 / lam), 1e6);
-          const double dt = s.dt_scale * sqrt(th);
-          s.theta = th;
-          s.dt = dt;
-          s.a = th / (th + dt);
-          s.c = dt / ((th + dt) * s.hd);
-        }
-      }
+      // critical damping of the mode of the state at this block boundary
+      if (!s.done && rq) adapt_damping(s, uu, uf, ur);
     }
   }
   __syncthreads();
@@ -262,6 +287,10 @@ template void launch_rq<double, double>(const double*, const double*, const doub
                                         double*, hipStream_t);
 template void launch_rq<double, float>(const double*, const float*, const double*, const StateRange*, int, int,
                                        double*, hipStream_t);
+
+void launch_adapt(SolveState* st, const double* prq, int rq_blocks, int ndes, hipStream_t s) {
+  hipLaunchKernelGGL(adapt_kernel, dim3(1), dim3(kBlock), 0, s, st, prq, rq_blocks, ndes);
+}
 
 void launch_setup(const SetupArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(setup_kernel, dim3(a.ndes), dim3(kWave), 0, s, a);

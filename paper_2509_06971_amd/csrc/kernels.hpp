@@ -184,6 +184,9 @@ template <typename U, typename R>
 void launch_rq(const U* u, const R* r, const double* F, const StateRange* ranges, int ndes, int bpd,
                double* prq, hipStream_t s);
 void launch_finalize(const FinalizeArgs& a, hipStream_t s);
+// Adaptive damping from the sums in prq, applied to every unfinished design
+// before a solve's first sweep.
+void launch_adapt(SolveState* st, const double* prq, int rq_blocks, int ndes, hipStream_t s);
 
 template <typename T>
 void launch_fill(T* p, long n, T value, hipStream_t s);

@@ -692,6 +692,38 @@ petto_status solve_plain(petto_ctx* c, const void* phi, void* u, void* v, const 
   const int nchk = ap->check_every;
   if (std::is_same<T, float>::value) PETTO_TRY(ensure_blocking(c, s, nchk));
   const bool adapt = ap->adapt != 0;
+  // adaptive damping: the residual of the state in u into the free ping-pong
+  // buffer, then the Rayleigh-quotient sums
+  const auto rq_pass = [=](hipStream_t st) {
+    if (c->physics == PETTO_ELASTIC) {
+      ElSweep<T> a{};
+      a.uin = uu;
+      a.v = ua;
+      a.E = E;
+      a.b = b;
+      if (c->ndim == 2) launch_el2d<T, kResid>(c->geom, a, st);
+      else launch_el3d<T, kResid>(c->geom, a, st);
+    } else {
+      HeatSweep<T> a{};
+      a.uin = uu;
+      a.v = ua;
+      a.k = E;
+      a.b = b;
+      a.des = c->d_des;
+      a.tiles = c->heat_lists.at(1).tiles;
+      a.dir = c->d_dir;
+      a.ntile = c->heat_lists.at(1).ntile;
+      launch_heat2d<T, kResid>(a, st);
+    }
+    launch_rq<T, T>(uu, ua, c->F64, c->d_srange, c->nprob, kRqBlocks, c->prq, st);
+  };
+  if (adapt) {
+    // a warm start begins at the damping of its own state (a state of zeros
+    // keeps the floor); the checks re-choose it after every block
+    rq_pass(s);
+    launch_adapt(c->st, c->prq, kRqBlocks, c->nprob, s);
+    HIP_TRY(hipGetLastError());
+  }
   std::function<void(hipStream_t)> body = [=](hipStream_t st) {
     const int* tile0 = nullptr;
     int nt = 0;
@@ -702,31 +734,7 @@ petto_status solve_plain(petto_ctx* c, const void* phi, void* u, void* v, const 
       tile0 = L->tile0;
       nt = L->ntile;
     }
-    if (adapt) {
-      // residual of the block-boundary state into the free ping-pong buffer, then
-      // the Rayleigh-quotient sums
-      if (c->physics == PETTO_ELASTIC) {
-        ElSweep<T> a{};
-        a.uin = uu;
-        a.v = ua;
-        a.E = E;
-        a.b = b;
-        if (c->ndim == 2) launch_el2d<T, kResid>(c->geom, a, st);
-        else launch_el3d<T, kResid>(c->geom, a, st);
-      } else {
-        HeatSweep<T> a{};
-        a.uin = uu;
-        a.v = ua;
-        a.k = E;
-        a.b = b;
-        a.des = c->d_des;
-        a.tiles = c->heat_lists.at(1).tiles;
-        a.dir = c->d_dir;
-        a.ntile = c->heat_lists.at(1).ntile;
-        launch_heat2d<T, kResid>(a, st);
-      }
-      launch_rq<T, T>(uu, ua, c->F64, c->d_srange, c->nprob, kRqBlocks, c->prq, st);
-    }
+    if (adapt) rq_pass(st);
     finalize(c, st, c->st, tile0, nt, 0, adapt);
   };
   std::vector<const void*> key = {uu, ua, vv, E, b, (const void*)(long)nchk, (const void*)(long)sizeof(T),

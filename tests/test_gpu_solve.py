@@ -194,3 +194,30 @@ def test_adaptive_damping_refined_fp32():
     ud = assembly.direct_solve(design.stiffness(E, prob), design.load_vector(prob), prob)
     assert rel_l2(host(u, prob.u_shape()), ud) < 1e-4
     ctx.close()
+
+
+def test_warm_started_adaptive_fp64_3d_design_steps():
+    """Two design steps of the multi-material 3D cantilever at 128x64x64 with
+    adaptive damping, FP64 plain against the FP32 refined mode: the warm-started
+    second solve of either converges, with sweep counts within 20 % of each
+    other (the damping of a warm start comes from its own state from the first
+    sweep on, in both modes)."""
+    require_gpu()
+    prob = W.multimaterial3d(128, 64, 64)
+    announce("adaptive warm start multimaterial3d_128x64x64")
+    counts = {}
+    for prec in ("fp32", "fp64"):
+        ctx = context(prob, prec)
+        phi = dev(W.initial_phi(prob), torch.float32 if prec == "fp32" else torch.float64)
+        u = ctx.new_state(torch.float64)
+        v = ctx.new_state()
+        g = ctx.new_cells()
+        apt = dict(theta=1.0, tol=1e-6, adapt=True, refine=prec == "fp32", max_iter=200000)
+        counts[prec] = []
+        for _ in range(2):
+            st, si, _, _ = ctx.step(phi, u, v, g, vol_frac=prob.vol_frac, apt=apt)
+            assert st == L.OK and si[0]["status"] == L.OK, (prec, si)
+            counts[prec].append(si[0]["iters"])
+        ctx.close()
+    for a, b in zip(counts["fp32"], counts["fp64"]):
+        assert abs(a - b) <= 0.2 * a, counts

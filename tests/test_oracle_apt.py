@@ -112,6 +112,29 @@ def test_adapted_theta_single_unknown():
     assert apt.adapted_theta(np.zeros(1), r, np.array([F]), 1.0, 1.0) is None
 
 
+def _scalar_sweeps(u, v, theta, dt, kappa, F, n):
+    for _ in range(n):
+        v = (theta * v + dt * (F - kappa * u)) / (theta + dt)
+        u = u + dt * v
+    return u, v
+
+
+@pytest.mark.parametrize("u0", [3.0, 0.0])
+def test_adaptive_damping_starts_from_the_state_it_is_given(u0):
+    """One unknown K = kappa, h^d = 1: a warm start (u0 != 0) runs its first
+    sweeps at the critical damping 1 / (4 kappa) of its own state; a start from
+    zero has no quotient and runs them at the floor.  Checked against the
+    damped-wave recurrence written out for the first block."""
+    kappa, F, floor = 0.02, 1.0, 1.0
+    dt_of = lambda th: 0.05 * np.sqrt(th)
+    res = apt.apt_solve(lambda u: F - kappa * u, np.array([u0]), dt=dt_of(floor), theta=floor, hd=1.0,
+                        fnorm=F, ncell=1, check_every=10, n_iter=10, adapt=(np.array([F]), dt_of))
+    th = 1.0 / (4 * kappa) if u0 != 0.0 else floor
+    u_want, v_want = _scalar_sweeps(u0, 0.0, th, dt_of(th), kappa, F, 10)
+    assert res.u[0] == pytest.approx(u_want, rel=1e-14)
+    assert res.v[0] == pytest.approx(v_want, rel=1e-14)
+
+
 def test_adaptive_damping_reaches_direct_solution_faster():
     prob = W.cantilever2d(16, 8)
     phi = W.initial_phi(prob)
