@@ -49,7 +49,8 @@ def parse():
     ap.add_argument("--workload", default="cantilever2d",
                     help="cantilever2d (design steps, the default line) or, for sweep throughput only: "
                          "heat_batch64, cantilever3d_NXxNYxNZ, multimaterial3d_NXxNYxNZ (e.g. 256x128x128, "
-                         "or 256x128x18 for one GPU's z-slab of an 8-way split with its halo layers)")
+                         "or 256x128x18 for one GPU's z-slab of an 8-way split with its halo layers); "
+                         "with --ttd-steps, the 3D workloads run design steps too")
     ap.add_argument("--sweeps", type=int, default=2000, help="sweep-throughput legs: sweeps to time")
     ap.add_argument("--adapt", action="store_true",
                     help="re-choose the damping at every check from the state's Rayleigh quotient")
@@ -66,6 +67,11 @@ def parse():
     ap.add_argument("--ttd-steps", type=int, default=0,
                     help="time to converged design: run this many design steps in FP32 (refined, graphs, "
                          "multi-sweep launches) and in FP64 (one sweep per launch, no graphs)")
+    ap.add_argument("--ttd-modes", default="fp32,fp64",
+                    help="time to converged design: the legs to run (fp32, fp64 or both)")
+    ap.add_argument("--max-iter", type=int, default=10**8,
+                    help="time to converged design: sweep cap per solve (a capped solve is reported "
+                         "as not converged)")
     return ap.parse_args()
 
 
@@ -90,7 +96,7 @@ def cpu_baseline(prob, phi0, sweeps):
             "seconds": round(dt, 3), "sweep_seconds": (t1 - t0) / sweeps,
             "sensitivity_and_phase_seconds": dt - (t1 - t0),
             "sample": f"{sweeps} sweeps from rest + 1 sensitivity + 1 phase update on the full "
-                      f"{prob.n[0]}x{prob.n[1]} grid (FP64 NumPy/SciPy; cores = CPU seconds per wall second, rounded)"}
+                      f"{'x'.join(str(n) for n in prob.n)} grid (FP64 NumPy/SciPy; cores = CPU seconds per wall second, rounded)"}
 
 
 # Algorithmic bytes per cell and sweep of the other FP32 sweep kernels: state and
@@ -202,19 +208,31 @@ def sweep_leg(args):
 
 
 def ttd_leg(args):
-    """Time to converged design on the 2D cantilever: the same number of design
-    steps (each relaxed to rho <= tol) in the FP32 production mode and in the FP64
-    plain mode, from the same start."""
+    """Time to converged design: the same number of design steps (each relaxed to
+    rho <= tol) in the FP32 production mode and in the FP64 plain mode, from the
+    same start, on the 2D cantilever or on a 3D workload (cantilever3d_NXxNYxNZ,
+    multimaterial3d_NXxNYxNZ)."""
     import numpy as np
     import torch
 
     import workloads as W
     from paper_2509_06971_amd.api import Context
+    from paper_2509_06971_amd.profile_run import make
 
-    prob = W.cantilever2d(args.nx, args.ny)
+    if args.workload == "cantilever2d":
+        prob = W.cantilever2d(args.nx, args.ny)
+        name = f"cantilever2d_{args.nx}x{args.ny}"
+    else:
+        probs = make(args.workload)
+        if len(probs) != 1 or not args.workload.startswith(("cantilever", "multimaterial")):
+            raise SystemExit(f"--ttd-steps: no design loop for workload {args.workload}")
+        prob, name = probs[0], args.workload
     phi0 = W.initial_phi(prob)
     res = {}
-    for mode in ("fp32", "fp64"):
+    modes = [m for m in args.ttd_modes.split(",") if m]
+    if not modes or any(m not in ("fp32", "fp64") for m in modes):
+        raise SystemExit(f"--ttd-modes: fp32 and/or fp64, not {args.ttd_modes}")
+    for mode in modes:
         ctx = Context(prob, mode)
         if mode == "fp64":
             ctx.set_blocking(1)
@@ -225,40 +243,45 @@ def ttd_leg(args):
         g = ctx.new_cells()
         comp = torch.zeros(2, dtype=torch.float64, device="cuda")
         apt = dict(theta=args.theta, tol=args.tol, check_every=100, refine=(mode == "fp32"),
-                   use_graph=(mode == "fp32"), adapt=args.adapt)
-        sweeps, hist = 0, []
+                   use_graph=(mode == "fp32"), adapt=args.adapt, max_iter=args.max_iter)
+        sweeps, hist, capped = 0, [], 0
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for s in range(args.ttd_steps):
             st, si, pi, _ = ctx.step(phi, u, v, g, vol_frac=prob.vol_frac, compliance=comp, apt=apt)
             sweeps += si[0]["iters"]
             hist.append(si[0]["iters"])
-            print(f"[ttd] {mode} step {s + 1}/{args.ttd_steps}: {si[0]['iters']} sweeps, "
-                  f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+            capped += si[0]["status"] == 1
+            print(f"[ttd] {mode} step {s + 1}/{args.ttd_steps}: {si[0]['iters']} sweeps, status {si[0]['status']}, "
+                  f"rho {si[0]['rel_res']:.3g}, theta {si[0]['theta']:.4g}, {time.perf_counter() - t0:.1f} s",
+                  file=sys.stderr, flush=True)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         res[mode] = {"seconds": wall, "sweeps": sweeps, "compliance": comp[0].item(),
-                     "energy2": comp[1].item(), "sweeps_per_step": hist,
+                     "energy2": comp[1].item(), "sweeps_per_step": hist, "capped_solves": capped,
                      "phi_final": phi.double().cpu().numpy()}
         ctx.close()
     # the oracle on the host, timed on a bounded sample and extrapolated to the
     # FP64 leg's recorded sweep counts (labelled as an extrapolation)
     cpu = None
-    if not args.no_cpu:
+    if not args.no_cpu and "fp64" in res:
         cpu = cpu_baseline(prob, phi0, args.cpu_sweeps)
         cpu["extrapolated_seconds"] = (cpu["sweep_seconds"] * res["fp64"]["sweeps"] +
                                        cpu["sensitivity_and_phase_seconds"] * args.ttd_steps)
         cpu["note"] = "extrapolated from the timed sample and the FP64 leg's sweep counts"
-    d_phi = float(np.abs(res["fp32"]["phi_final"] - res["fp64"]["phi_final"]).max())
+    both = len(res) == 2
+    d_phi = float(np.abs(res["fp32"]["phi_final"] - res["fp64"]["phi_final"]).max()) if both else None
     for m in res:
         res[m].pop("phi_final")
     out = {"metric": "time to converged design FP32 vs FP64", "config": {
-        "workload": f"cantilever2d_{args.nx}x{args.ny}", "design_steps": args.ttd_steps, "tol": args.tol,
-        "theta": args.theta, "adaptive_damping": args.adapt},
-        "fp32_refined_graph": res["fp32"], "fp64_plain": res["fp64"],
-        "speedup": res["fp64"]["seconds"] / res["fp32"]["seconds"],
-        "rel_compliance_diff": abs(res["fp32"]["compliance"] - res["fp64"]["compliance"]) /
-        res["fp64"]["compliance"], "max_design_diff": d_phi, "cpu_oracle": cpu}
+        "workload": name, "cells": prob.ncell, "design_steps": args.ttd_steps, "tol": args.tol,
+        "theta": args.theta, "adaptive_damping": args.adapt, "max_iter": args.max_iter},
+        "fp32_refined_graph": res.get("fp32"), "fp64_plain": res.get("fp64"), "cpu_oracle": cpu}
+    if both:
+        out["speedup"] = res["fp64"]["seconds"] / res["fp32"]["seconds"]
+        out["rel_compliance_diff"] = (abs(res["fp32"]["compliance"] - res["fp64"]["compliance"]) /
+                                      res["fp64"]["compliance"])
+        out["max_design_diff"] = d_phi
     print(json.dumps(out))
 
 
