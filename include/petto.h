@@ -113,10 +113,12 @@ typedef struct {
  *  use_graph: replay captured blocks of check_every sweeps instead of launching
  *  each sweep from the host.  replay_iters > 0: run exactly that many sweeps (a
  *  multiple of check_every), ignoring tol.
- *  adapt: after every check block re-choose the damping from the state u at the
- *  block boundary: theta = max(theta_given, 1 / (4 lam)) with the Rayleigh quotient
- *  lam = u.K u / (h^d u.u), which critically damps the mode of the current state
- *  (needs dt <= 0: the step follows theta).  The velocity carries over. */
+ *  adapt: choose the damping from the starting state u before the first sweep
+ *  (a state of zeros keeps theta_given) and re-choose it from the state at every
+ *  check block boundary: theta = max(theta_given, 1 / (4 lam)) with the Rayleigh
+ *  quotient lam = u.K u / (h^d u.u), which critically damps the mode of the
+ *  current state (needs dt <= 0: the step follows theta).  The velocity carries
+ *  over. */
 typedef struct {
   double theta;
   double dt;
