@@ -301,7 +301,8 @@ __device__ __forceinline__ void zero_slot(const Out<T, MODE>& o, unsigned off) {
 // also takes the face column i = nx (only u_x lives there) through TY + 1 threads
 // of its first wave; y-tiles of TY rows cover j < ny, and a tile ending at
 // j = ny - 1 also takes the face row j = ny (only u_y) through its last wave;
-// z-tiles of KZ layers, the last one running through layer nz.
+// z-tiles of KZ layers, the last one also finishing the top layer nz (only u_z)
+// in a short epilogue.
 template <typename T, int TY, int KZ, int MODE>
 __global__ __launch_bounds__(TX * TY, 4) void el3d_stream_kernel(ElGeom g, ElSweep<T> A, int tiles_x, int tiles_y,
                                                               int ntiles) {
@@ -383,7 +384,8 @@ __global__ __launch_bounds__(TX * TY, 4) void el3d_stream_kernel(ElGeom g, ElSwe
   // LDS indices of the face-column and face-row slots (a valid index for every lane)
   const int qxe = (own & kXface) ? (1 + (int)threadIdx.x) * LX + XA : 0;
   const int qye = (own & kYface) ? (TY + 1) * LX + a : 0;
-  const int kend = (tz == ntiles / txy - 1) ? nz + 1 : k0 + KZ;
+  const bool top_tile = tz == ntiles / txy - 1;
+  const int kend = top_tile ? nz : k0 + KZ;
   // prologue: planes k0-1 (into buffer 1) and k0 (buffer 0); xz/yz shear at z = k0
   // into buffer 0; sigma_zz of the own cell at k0-1; plane k0+1 fetched ahead
   // (the loads of all three planes are issued before the first wait, so the
@@ -558,10 +560,63 @@ __global__ __launch_bounds__(TX * TY, 4) void el3d_stream_kernel(ElGeom g, ElSwe
     // the next store writes the plane read before the barrier above, and the
     // stress planes read here are rewritten only after the next barrier
   };
+  // the top layer k = nz holds only u_z (its u_x, u_y slots are padding).  Its
+  // residual needs sigma_zz of the cell below (szz_prev, the cell above is
+  // outside) and the xz / yz shear at z = nz, which the layer below formed
+  // before its second barrier, and the state plane nz, staged by that layer: no
+  // staging, stress pass or barrier of its own, so the last z-tile takes no
+  // longer than the others.
+  auto top = [&](auto parity) {
+    constexpr int cur = decltype(parity)::value;
+    const long kS = (long)nz * S;
+    T vz = T(0);
+    if (MODE == kSweep || MODE == kCheck) vz = ldo(A.v + kS + 2 * pl, po);
+    const T bz = ldo(A.b + kS + 2 * pl, po);
+    const T* TXZc = &sm.txz[cur][0][0];
+    const T* TYZc = &sm.tyz[cur][0][0];
+    const T uz = (&sm.u[cur][2][0][0])[qo];
+    const T rz = el3d::residual<T>(bz, h2, T(0), szz_prev, TXZc[qo + 1], TXZc[qo], TYZc[qo + LX], TYZc[qo]);
+    Out<T, MODE> o[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      o[c].v = MODE == kRefine ? nullptr : A.v + c * pl + kS;
+      o[c].u = MODE == kSweep || MODE == kCheck ? A.uout + c * pl + kS : nullptr;
+      o[c].r32 = MODE == kRefine ? A.b32 + c * pl + kS : nullptr;
+    }
+    unsigned ow = own;
+    asm volatile("" : "+v"(ow));
+    if (ow & kIn) {
+      zero_slot<T, MODE>(o[0], po);
+      zero_slot<T, MODE>(o[1], po);
+      if (ow & kOkz) {
+        bool fixc = g.fixn[5] != 0;
+        if (g.pins != nullptr) fixc = fixc || pinned3s(g.pins, 2 * pl + kS + po / W);
+        finish<T, MODE>(o[2], po, fixc, rz, uz, vz, ca, cc, dt, acc);
+      } else {
+        zero_slot<T, MODE>(o[2], po);
+      }
+    }
+    // face column and face row slots of the top layer are padding
+    if (edge_duty) {
+      if (ow & kXface) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) zero_slot<T, MODE>(o[c], peo);
+      }
+      if (ow & kYface) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) zero_slot<T, MODE>(o[c], pfo);
+      }
+    }
+  };
   for (int k = k0; k < kend; k += 2) {
     layer(std::integral_constant<int, 0>(), k);
     if (k + 1 >= kend) break;
     layer(std::integral_constant<int, 1>(), k + 1);
+  }
+  if (top_tile) {
+    // the buffer parity of layer nz follows that of the last layer run
+    if (((nz - k0) & 1) == 0) top(std::integral_constant<int, 0>());
+    else top(std::integral_constant<int, 1>());
   }
   if (MODE == kCheck || MODE == kRefine) {
     const double s = block_sum(acc, sm.red);
