@@ -186,6 +186,36 @@ def test_full_size_sweeps_parity(name, make):
     assert info[0]["rel_res"] == pytest.approx(res.rho, rel=1e-3)
 
 
+def test_full_size_multimaterial3d_sweeps_parity():
+    """The multi-material 3D configuration at full size (256x128x128, 12.8 M
+    unknowns) in the launch configuration the bench times (FP32, the automatic
+    tiling: 64x8x8 columns, two rounds of workgroups): 4 sweeps from a random
+    state against 4 FP64 sweeps on the oracle's matrix-free residual, every
+    unknown."""
+    require_gpu()
+    prob = W.multimaterial3d(256, 128, 128)
+    announce("full-size sweeps multimaterial3d_256x128x128")
+    phi = _fp32(W.random_phi(prob, 12, 0.05, 1.0))
+    u0 = _fp32(W.random_u(prob, 13, scale=1e-3))
+    ctx = context(prob, "fp32")
+    u = dev(u0, torch.float32)
+    v = ctx.new_state()
+    st, info = ctx.solve(dev(phi, torch.float32), u, v, theta=1.0, replay_iters=4, check_every=4)
+    assert info[0]["iters"] == 4
+    got = host(u, prob.u_shape())
+    tiling = ctx.tile3d()
+    ctx.close()
+    E = elastic.modulus(phi, prob)
+    F = design.load_vector(prob)
+    dt = apt.default_dt(prob.h, prob.ndim, design.wave_modulus_max(E, prob), 1.0)
+    assert info[0]["dt"] == pytest.approx(dt, rel=1e-6)
+    res = apt.apt_solve(lambda x: elastic.residual(x, E, prob, F), u0, dt=dt, theta=1.0, hd=prob.h ** 3,
+                        fnorm=float(np.sqrt(np.sum(F * F))), ncell=prob.ncell, check_every=4, n_iter=4)
+    err = rel_l2(got, res.u)
+    assert err < 2e-5, (tiling, err)
+    assert info[0]["rel_res"] == pytest.approx(res.rho, rel=1e-3)
+
+
 def test_full_size_heat_batch_sweeps_parity():
     """The 64-design heat batch at full size (22.0 M cells), 20 FP32 sweeps in the
     bench's launch configuration; four seeded designs compared with the oracle on
