@@ -68,7 +68,9 @@ def parse():
                     help="time to converged design: run this many design steps in FP32 (refined, graphs, "
                          "multi-sweep launches) and in FP64 (one sweep per launch, no graphs)")
     ap.add_argument("--ttd-modes", default="fp32,fp64",
-                    help="time to converged design: the legs to run (fp32, fp64 or both)")
+                    help="time to converged design: the legs to run, of fp32 (refined, graphs, multi-sweep "
+                         "launches), fp64 (one sweep per launch, no graphs) and fp64g (FP64 with the same "
+                         "graphs and, in 2D, the fastest sweeps per launch)")
     ap.add_argument("--max-iter", type=int, default=10**8,
                     help="time to converged design: sweep cap per solve (a capped solve is reported "
                          "as not converged)")
@@ -207,11 +209,31 @@ def sweep_leg(args):
     print(json.dumps(out))
 
 
+def fastest_fp64_blocking(ctx, prob, phi):
+    """Sweeps per launch for an FP64 2D context: the fastest of 1, 2, 4 and 5 on
+    1000 graph-replayed sweeps of the design at hand."""
+    import torch
+    best = None
+    for k in (1, 2, 4, 5):
+        ctx.set_blocking(k)
+        u, v = ctx.new_state(), ctx.new_state()
+        ctx.solve(phi, u, v, theta=1.0, replay_iters=200, check_every=100, use_graph=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.solve(phi, u, v, theta=1.0, replay_iters=1000, check_every=100, use_graph=True)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        if best is None or dt < best[1]:
+            best = (k, dt)
+    ctx.set_blocking(best[0])
+    return best[0]
+
+
 def ttd_leg(args):
     """Time to converged design: the same number of design steps (each relaxed to
-    rho <= tol) in the FP32 production mode and in the FP64 plain mode, from the
-    same start, on the 2D cantilever or on a 3D workload (cantilever3d_NXxNYxNZ,
-    multimaterial3d_NXxNYxNZ)."""
+    rho <= tol) in the FP32 production mode and in FP64 (plain, and optionally
+    with the same launch machinery), from the same start, on the 2D cantilever or
+    on a 3D workload (cantilever3d_NXxNYxNZ, multimaterial3d_NXxNYxNZ)."""
     import numpy as np
     import torch
 
@@ -230,20 +252,23 @@ def ttd_leg(args):
     phi0 = W.initial_phi(prob)
     res = {}
     modes = [m for m in args.ttd_modes.split(",") if m]
-    if not modes or any(m not in ("fp32", "fp64") for m in modes):
-        raise SystemExit(f"--ttd-modes: fp32 and/or fp64, not {args.ttd_modes}")
+    if not modes or any(m not in ("fp32", "fp64", "fp64g") for m in modes):
+        raise SystemExit(f"--ttd-modes: of fp32, fp64 and fp64g, not {args.ttd_modes}")
+    blocking = {}
     for mode in modes:
-        ctx = Context(prob, mode)
-        if mode == "fp64":
-            ctx.set_blocking(1)
+        ctx = Context(prob, "fp32" if mode == "fp32" else "fp64")
         dtype = torch.float32 if mode == "fp32" else torch.float64
         phi = torch.tensor(phi0.ravel(), dtype=dtype, device="cuda")
+        if mode == "fp64":
+            ctx.set_blocking(1)
+        elif mode == "fp64g" and prob.ndim == 2:
+            blocking[mode] = fastest_fp64_blocking(ctx, prob, phi)
         u = ctx.new_state(torch.float64)
         v = ctx.new_state()
         g = ctx.new_cells()
         comp = torch.zeros(2, dtype=torch.float64, device="cuda")
         apt = dict(theta=args.theta, tol=args.tol, check_every=100, refine=(mode == "fp32"),
-                   use_graph=(mode == "fp32"), adapt=args.adapt, max_iter=args.max_iter)
+                   use_graph=(mode != "fp64"), adapt=args.adapt, max_iter=args.max_iter)
         sweeps, hist, capped = 0, [], 0
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -269,19 +294,28 @@ def ttd_leg(args):
         cpu["extrapolated_seconds"] = (cpu["sweep_seconds"] * res["fp64"]["sweeps"] +
                                        cpu["sensitivity_and_phase_seconds"] * args.ttd_steps)
         cpu["note"] = "extrapolated from the timed sample and the FP64 leg's sweep counts"
-    both = len(res) == 2
+    both = "fp32" in res and "fp64" in res
     d_phi = float(np.abs(res["fp32"]["phi_final"] - res["fp64"]["phi_final"]).max()) if both else None
+    d_g = (float(np.abs(res["fp64g"]["phi_final"] - res["fp64"]["phi_final"]).max())
+           if "fp64g" in res and "fp64" in res else None)
     for m in res:
         res[m].pop("phi_final")
+    if "fp64g" in res:
+        res["fp64g"]["sweeps_per_launch"] = blocking.get("fp64g", 1)
     out = {"metric": "time to converged design FP32 vs FP64", "config": {
         "workload": name, "cells": prob.ncell, "design_steps": args.ttd_steps, "tol": args.tol,
         "theta": args.theta, "adaptive_damping": args.adapt, "max_iter": args.max_iter},
-        "fp32_refined_graph": res.get("fp32"), "fp64_plain": res.get("fp64"), "cpu_oracle": cpu}
+        "fp32_refined_graph": res.get("fp32"), "fp64_plain": res.get("fp64"), "fp64_graph": res.get("fp64g"),
+        "cpu_oracle": cpu}
     if both:
         out["speedup"] = res["fp64"]["seconds"] / res["fp32"]["seconds"]
         out["rel_compliance_diff"] = (abs(res["fp32"]["compliance"] - res["fp64"]["compliance"]) /
                                       res["fp64"]["compliance"])
         out["max_design_diff"] = d_phi
+    if "fp32" in res and "fp64g" in res:
+        out["speedup_vs_fp64_graph"] = res["fp64g"]["seconds"] / res["fp32"]["seconds"]
+    if d_g is not None:
+        out["fp64_graph_vs_plain_max_design_diff"] = d_g
     print(json.dumps(out))
 
 
