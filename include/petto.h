@@ -225,7 +225,9 @@ petto_status petto_residual(petto_ctx *ctx, const void *phi, const void *u, void
  * with the cell bilinear energy form B_c (B_c(u,u) = 2 W_c), w = u when w is NULL
  * (self-adjoint compliance).  u and w are double when `state_fp64` is nonzero,
  * else context precision.  compliance (device, double[2*nprob], may be NULL)
- * receives {F.u, 2 Pi(u)} per design.  Asynchronous on stream. */
+ * receives {F.u, 2 Pi(u)} per design.  Asynchronous on stream.  The context's
+ * partial-sum buffers are sized for this launch at creation; should they not
+ * fit, the call returns PETTO_ERR_UNSUPPORTED before launching anything. */
 petto_status petto_adjoint(petto_ctx *ctx, const void *phi, const void *u, const void *w,
                            int32_t state_fp64, void *grad_phi, double *compliance, void *stream);
 
