@@ -153,13 +153,16 @@ def test_two_runs_bit_identical():
     ctx.close()
 
 
-def test_adaptive_damping_matches_oracle():
-    """Damping re-chosen at every check from the Rayleigh quotient of the state:
-    the FP64 GPU solve stops on the oracle's sweep with the oracle's state, from
-    rest and warm-started after a design change."""
+@pytest.mark.parametrize("name,make", [("cant2d", lambda: W.cantilever2d(64, 32)),
+                                       ("multi3d", lambda: W.multimaterial3d(24, 10, 8))])
+def test_adaptive_damping_matches_oracle(name, make):
+    """Damping chosen from the starting state and re-chosen at every check from
+    the Rayleigh quotient of the state: the FP64 GPU solve stops on the oracle's
+    sweep with the oracle's state, from rest and warm-started after a design
+    change."""
     require_gpu()
-    prob = W.cantilever2d(64, 32)
-    announce("adaptive damping fp64")
+    prob = make()
+    announce(f"adaptive damping fp64 {name}")
     ctx = context(prob, "fp64")
     phi0 = W.initial_phi(prob)
     phi1 = W.random_phi(prob, 4, 0.3, 1.0)
