@@ -395,8 +395,8 @@ def paper_leg(args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
-                                   "(multi-GPU sharding is described in DESIGN.md, not implemented)"}))
+        print(json.dumps({"error": "petto runs on one GPU; --gpus must be 1 "
+                                   "(sharding a design across GPUs is not implemented)"}))
         sys.exit(2)
     if args.ttd_steps > 0:
         ttd_leg(args)

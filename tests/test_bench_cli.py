@@ -17,6 +17,24 @@ def test_more_than_one_gpu_is_refused():
     assert "one GPU" in json.loads(p.stdout.strip().splitlines()[-1])["error"]
 
 
+def test_unknown_time_to_design_leg_is_refused():
+    p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--ttd-steps", "1", "--ttd-modes", "fp16"],
+                       capture_output=True, text=True, timeout=300)
+    assert p.returncode != 0 and "--ttd-modes" in p.stderr
+
+
+def test_recorded_traffic_is_current():
+    """Every committed counter record was taken on the kernel sources as they
+    stand (a stale record makes the bench report its traffic as null)."""
+    with open(os.path.join(ROOT, "profiles", "traffic.json")) as fh:
+        recs = json.load(fh)
+    assert recs
+    for key, rec in recs.items():
+        name = key.split(" @ ")[0]
+        family = "heat" if name.startswith("heat") else ("el3d" if name.startswith("el3d") else "el2d")
+        assert rec["source_digest"] == bench.source_digest(family), key
+
+
 def test_bytes_per_cell():
     assert bench.bytes_per_cell("heat_batch64") == 20
     assert bench.bytes_per_cell("multimaterial3d_256x128x18") == 64
