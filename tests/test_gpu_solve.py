@@ -79,6 +79,36 @@ def test_heat_batch_solve_matches_direct():
     ctx.close()
 
 
+def test_heat_batch_adaptive_damping_matches_oracle():
+    """Adaptive damping on a batch of heat designs: each design takes its own
+    damping from its own state (before its first sweep, then at every check).
+    From rest and warm-started on new designs, the FP64 batch solve stops every
+    design on the oracle's sweep, with the oracle's damping and state."""
+    require_gpu()
+    probs, phis, _ = W.heat_batch_small()
+    announce("heat batch adaptive damping fp64")
+    phis2 = [W.random_phi(p, 100 + d, 0.0, 1.0) for d, p in enumerate(probs)]
+    ctx = context(probs, "fp64")
+    u = ctx.new_state()
+    v = ctx.new_state()
+    uo = [np.zeros(p.cell_shape()) for p in probs]
+    for batch in (phis, phis2):
+        phi_t = dev(np.concatenate([x.ravel() for x in batch]), torch.float64)
+        st, info = ctx.solve(phi_t, u, v, theta=0.1, tol=1e-8, check_every=50, adapt=True)
+        assert st == L.OK
+        got = host(u)
+        for d, p in enumerate(probs):
+            res, _ = design.solve(batch[d], p, u0=uo[d],
+                                  params=design.AptParams(theta=0.1, tol=1e-8, check_every=50, adapt=True))
+            assert res.converged
+            assert info[d]["iters"] == res.iters, d
+            assert info[d]["theta"] == pytest.approx(res.theta, rel=1e-9), d
+            o0, o1 = ctx.offset(d, 1), ctx.offset(d + 1, 1)
+            assert rel_l2(got[o0:o1].reshape(p.cell_shape()), res.u) < 1e-10, d
+            uo[d] = res.u
+    ctx.close()
+
+
 def test_heat_batch_fp32_refined():
     require_gpu()
     probs, phis, _ = W.heat_batch_small()
