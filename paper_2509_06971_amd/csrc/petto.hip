@@ -47,7 +47,10 @@ petto_status fail(petto_status s, const char* fmt, ...) {
   } while (0)
 
 constexpr int kBpd = 256;          // material-kernel blocks per design
-constexpr int kRqBlocks = 256;     // Rayleigh-quotient blocks per design
+// Rayleigh-quotient blocks per design: about one per 4096 unknowns of the
+// largest design, so that the pass over a large state fills the chip
+constexpr long kRqPerBlock = 4096;
+constexpr int kRqBlocksMin = 64, kRqBlocksMax = 1024;
 constexpr int kGroup = 4;          // check blocks per graph launch
 constexpr int kMaxOuter = 64;      // refinement: correction solves per call
 constexpr double kDivFactor = 1e4;
@@ -91,7 +94,8 @@ struct petto_ctx {
   double* d_fnorm = nullptr;
   double* d_h = nullptr;
   StateRange* d_srange = nullptr;      // per-design state ranges (Rayleigh-quotient sums)
-  double* prq = nullptr;               // [nprob][kRqBlocks][3]
+  double* prq = nullptr;               // [nprob][rq_blocks][3]
+  int rq_blocks = kRqBlocksMin;
   std::vector<double> fnorm;
   double m0 = 1.0;
   // workspace
@@ -559,7 +563,7 @@ void finalize(const petto_ctx* c, hipStream_t s, SolveState* st, const int* tile
               bool adapt = false) {
   FinalizeArgs f{};
   f.prq = adapt ? c->prq : nullptr;
-  f.rq_blocks = kRqBlocks;
+  f.rq_blocks = c->rq_blocks;
   f.st = st;
   f.partial = c->partial;
   f.tile0 = tile0;
@@ -715,13 +719,13 @@ petto_status solve_plain(petto_ctx* c, const void* phi, void* u, void* v, const 
       a.ntile = c->heat_lists.at(1).ntile;
       launch_heat2d<T, kResid>(a, st);
     }
-    launch_rq<T, T>(uu, ua, c->F64, c->d_srange, c->nprob, kRqBlocks, c->prq, st);
+    launch_rq<T, T>(uu, ua, c->F64, c->d_srange, c->nprob, c->rq_blocks, c->prq, st);
   };
   if (adapt) {
     // a warm start begins at the damping of its own state (a state of zeros
     // keeps the floor); the checks re-choose it after every block
     rq_pass(s);
-    launch_adapt(c->st, c->prq, kRqBlocks, c->nprob, s);
+    launch_adapt(c->st, c->prq, c->rq_blocks, c->nprob, s);
     HIP_TRY(hipGetLastError());
   }
   std::function<void(hipStream_t)> body = [=](hipStream_t st) {
@@ -811,7 +815,7 @@ petto_status solve_refine(petto_ctx* c, const void* phi, void* u, void* v, const
       a.ntile = c->heat_lists.at(1).ntile;
       launch_heat2d<double, kRefine>(a, st);
     }
-    if (adapt) launch_rq<double, float>(u64, c->b32, c->F64, c->d_srange, c->nprob, kRqBlocks, c->prq, st);
+    if (adapt) launch_rq<double, float>(u64, c->b32, c->F64, c->d_srange, c->nprob, c->rq_blocks, c->prq, st);
     if (c->physics == PETTO_ELASTIC) finalize(c, st, c->st, nullptr, el_tiles_for(c, true), 1, adapt);
     else finalize(c, st, c->st, c->heat_lists.at(1).tile0, c->heat_lists.at(1).ntile, 1, adapt);
     if (c->physics == PETTO_ELASTIC) elastic_sweeps<float>(c, st, da, db, v32, E, b, c->st, nchk);
@@ -1211,7 +1215,11 @@ petto_status petto_create(const petto_problem* probs, int32_t nprob, int32_t pre
       for (int d = 0; d < nprob; ++d) sr.push_back({c->h_des[d].off, (long)c->h_des[d].nx * c->h_des[d].ny,
                                                     c->h_des[d].fsrc});
     PETTO_TRY(upload(c, &c->d_srange, sr));
-    PETTO_TRY(dalloc_t(c, &c->prq, (size_t)nprob * kRqBlocks * 3));
+    long maxn = 0;
+    for (const StateRange& r : sr) maxn = std::max(maxn, r.n);
+    const long rqb = (maxn + kRqPerBlock - 1) / kRqPerBlock;
+    c->rq_blocks = (int)std::min<long>(kRqBlocksMax, std::max<long>(kRqBlocksMin, rqb));
+    PETTO_TRY(dalloc_t(c, &c->prq, (size_t)nprob * c->rq_blocks * 3));
     PETTO_TRY(dalloc(c, &c->ualt, c->nstate * es));
     PETTO_TRY(dalloc(c, &c->valt, c->nstate * es));
     PETTO_TRY(dalloc(c, &c->E, c->ncell * es));
