@@ -153,7 +153,7 @@ def kernel_roofline(ctx, bytes_per_sweep, family, workload, launches=200):
     elif family == "heat":
         name = f"heat2d_tb_kernel<float, {k}, false>" if k > 1 else "heat2d_kernel<float, 0>"
     else:
-        ty, kz = {1: (8, 8), 2: (4, 4), 3: (4, 2)}[ctx.tile3d()]
+        ty, kz = {1: (8, 16), 2: (4, 4), 3: (4, 2)}[ctx.tile3d()]
         name = f"el3d_stream_kernel<float, {ty}, {kz}, 0>"
     achieved = bytes_per_sweep * k / (ms * 1e-3) / 1e9
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -272,8 +272,8 @@ petto_status petto_set_blocking(petto_ctx *ctx, int32_t k);
 int32_t petto_blocking(const petto_ctx *ctx);
 
 /* Tiling of the 3D elastic sweeps (streamed along z, Eqs. 3.6 and 3.12 in 3D):
- * t = 1: columns of 64 x 8 positions (FP64: 64 x 4) through 8 layers, the fewest
- * halo bytes; t = 2: columns of 64 x 4 positions through 4 layers and t = 3:
+ * t = 1: columns of 64 x 8 positions through 16 layers (FP64: 64 x 4 through 8),
+ * the fewest halo bytes; t = 2: columns of 64 x 4 positions through 4 layers and t = 3:
  * through 2 layers, more workgroups for small grids; t = 0: choose as at
  * creation (t = 1 when it gives at least two workgroups per compute unit, else
  * whichever of t = 2 and t = 3 needs fewer rounds of resident workgroups times

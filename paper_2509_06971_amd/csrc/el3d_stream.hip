@@ -625,11 +625,13 @@ __global__ __launch_bounds__(TX * TY, 4) void el3d_stream_kernel(ElGeom g, ElSwe
 }
 
 // Three tilings per precision: columns of 64 x TY positions streamed through KZ
-// layers.  The large one moves the fewest halo bytes; the smaller ones give
-// small grids enough workgroups to fill the chip (the shortest columns trade
-// more z-halo planes, mostly L2 hits, for twice the workgroups).
+// layers.  The large one moves the fewest halo bytes (in FP32 its 16 layers put
+// a 256x128x128 grid in one round of two resident workgroups per compute unit,
+// with one prologue per column); the smaller ones give small grids enough
+// workgroups to fill the chip (the shortest columns trade more z-halo planes,
+// mostly L2 hits, for twice the workgroups).
 template <typename T, int V> struct Cfg3;
-template <> struct Cfg3<float, 1> { static constexpr int TY = 8, KZ = 8; };
+template <> struct Cfg3<float, 1> { static constexpr int TY = 8, KZ = 16; };
 template <> struct Cfg3<float, 2> { static constexpr int TY = 4, KZ = 4; };
 template <> struct Cfg3<float, 3> { static constexpr int TY = 4, KZ = 2; };
 template <> struct Cfg3<double, 1> { static constexpr int TY = 4, KZ = 8; };
