@@ -212,20 +212,37 @@ class PhaseInfo:
     gmax: list = field(default_factory=list)
 
 
+def sensitivity_step(phi_m, g_m, alpha_h):
+    """Eqs. (3.2)-(3.3) without the penalty terms: the sensitivity is divided by its
+    largest magnitude over the cells of the phase, and the design moves against it
+    by alpha_h (downhill for the compliance, whose sensitivity g = dC/dphi this is).
+    Returns (phi', max|g|); a zero sensitivity leaves the phase unchanged."""
+    gmax = float(np.max(np.abs(g_m)))
+    ghat = g_m / gmax if gmax > 0 else np.zeros_like(g_m)
+    return phi_m - alpha_h * ghat, gmax
+
+
+def allen_cahn_step(p, h, gamma, dt_ac):
+    """One forward-Euler step of the Allen-Cahn gradient flow of the interface
+    energy of Section 2.4 (double well of Eq. (2.15) plus gamma/2 |grad phi|^2,
+    mobility 1): phi <- phi - dt_ac (w'(phi) - gamma Lap_h phi), with the mirror
+    (no-flux) Laplacian."""
+    return p - dt_ac * (double_well_derivative(p) - gamma * laplacian_mirror(p, h))
+
+
 def phase_update(phi, g, prob, params=PhaseParams()):
-    """Normalised sensitivity step, Allen-Cahn step, exact volume projection."""
+    """Normalised sensitivity step, Allen-Cahn step, exact volume projection.
+    ``params.dt_ac`` None selects the default step; 0 skips the Allen-Cahn step."""
     h, nd = prob.h, prob.ndim
-    dt_ac = params.dt_ac if params.dt_ac else default_dt_ac(h, nd, params.gamma)
+    dt_ac = params.dt_ac if params.dt_ac is not None else default_dt_ac(h, nd, params.gamma)
     vf = params.vol_frac if params.vol_frac else prob.vol_frac
     out = np.empty_like(phi)
     info = PhaseInfo()
     used = np.zeros(phi.shape[1:])
     N = phi[0].size
     for m in range(phi.shape[0]):
-        gmax = float(np.max(np.abs(g[m])))
-        ghat = g[m] / gmax if gmax > 0 else np.zeros_like(g[m])
-        p1 = phi[m] - params.alpha_h * ghat
-        p2 = p1 - dt_ac * (double_well_derivative(p1) - params.gamma * laplacian_mirror(p1, h))
+        p1, gmax = sensitivity_step(phi[m], g[m], params.alpha_h)
+        p2 = allen_cahn_step(p1, h, params.gamma, dt_ac) if dt_ac != 0.0 else p1
         lb, ub = region_bounds(prob, m, used)
         s = bisect_shift(p2, ub, vf[m] * N, params.bisect_iters, lb)
         out[m] = np.clip(p2 + s, lb, ub)
