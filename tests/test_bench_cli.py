@@ -36,9 +36,21 @@ def test_recorded_traffic_is_current():
 
 
 def test_bytes_per_cell():
-    assert bench.bytes_per_cell("heat_batch64") == 20
-    assert bench.bytes_per_cell("multimaterial3d_256x128x18") == 64
-    assert bench.bytes_per_cell("cantilever2d_1024x512") == 44
+    """Algorithmic bytes per cell and sweep: state and velocity read and written
+    once plus one material value (FP32)."""
+    assert bench.bytes_per_cell("heat_batch64") == 4 * (2 + 2) + 4
+    assert bench.bytes_per_cell("multimaterial3d_256x128x18") == 4 * (6 + 6) + 4
+    assert bench.bytes_per_cell("cantilever3d_128x64x64") == 52
+    assert bench.bytes_per_cell("cantilever2d_1024x512") == 4 * (4 + 4) + 4
+    assert bench.RHS_BYTES_PER_CELL["el2d"] == 8 and bench.RHS_BYTES_PER_CELL["el3d"] == 12
+
+
+def test_oracle_extrapolation_uses_the_fp64_sweeps():
+    cpu = {"sweep_seconds": 0.01, "sensitivity_and_phase_seconds": 0.5, "cores": 1, "sample": "s"}
+    ttd = {"config": {"design_steps": 4}, "fp64_plain": {"sweeps": 1000}}
+    ex = bench.oracle_extrapolation(cpu, ttd)
+    assert ex["seconds"] == 0.01 * 1000 + 0.5 * 4 and ex["cores"] == 1
+    assert bench.oracle_extrapolation(None, ttd) is None
 
 
 def test_recorded_traffic_needs_matching_sources(tmp_path, monkeypatch):

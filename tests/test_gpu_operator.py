@@ -216,16 +216,16 @@ def test_full_size_multimaterial3d_sweeps_parity():
     assert info[0]["rel_res"] == pytest.approx(res.rho, rel=1e-3)
 
 
-def test_full_size_heat_batch_sweeps_parity():
+@pytest.mark.timeout(900)
+@pytest.mark.oracle_job("heat_batch64_20")
+def test_full_size_heat_batch_sweeps_parity(oracle_jobs):
     """The 64-design heat batch at full size (22.0 M cells), 20 FP32 sweeps in the
-    bench's launch configuration; four seeded designs compared with the oracle on
-    every cell, the rest checked for finiteness."""
+    bench's launch configuration, every design compared with the oracle on every
+    cell (the oracle's sweeps run in a child process started at session start)."""
     require_gpu()
-    probs, phis, _ = W.heat_batch()
+    from oracle_jobs import heat_batch_start
+    probs, phis, u0 = heat_batch_start()
     announce("full-size heat batch sweeps")
-    rng = np.random.default_rng(14)
-    u0 = [_fp32(rng.uniform(0.0, 1e-2, p.cell_shape())) for p in probs]
-    phis = [_fp32(x) for x in phis]
     ctx = context(probs, "fp32")
     phi_t = dev(np.concatenate([x.ravel() for x in phis]), torch.float32)
     ctx.solve(phi_t, ctx.new_state(), ctx.new_state(), theta=1.0, replay_iters=20, check_every=20)
@@ -233,11 +233,10 @@ def test_full_size_heat_batch_sweeps_parity():
     v = ctx.new_state()
     st, info = ctx.solve(phi_t, u, v, theta=1.0, replay_iters=20, check_every=20)
     got = host(u)
-    assert np.all(np.isfinite(got))
     offs = [(ctx.offset(d, 1), ctx.offset(d + 1, 1)) for d in range(len(probs))]
     ctx.close()
-    for d in sorted(rng.choice(len(probs), 4, replace=False)):
-        p = probs[d]
-        res, _ = design.solve(phis[d], p, u0=u0[d], params=design.AptParams(theta=1.0, check_every=20), n_iter=20)
+    want = oracle_jobs.result("heat_batch64_20")["u"]
+    assert got.shape == want.shape
+    for d, p in enumerate(probs):
         o0, o1 = offs[d]
-        assert rel_l2(got[o0:o1].reshape(p.cell_shape()), res.u) < 2e-5, d
+        assert rel_l2(got[o0:o1], want[o0:o1]) < 2e-5, d
