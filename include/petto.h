@@ -231,6 +231,22 @@ petto_status petto_residual(petto_ctx *ctx, const void *phi, const void *u, void
 petto_status petto_adjoint(petto_ctx *ctx, const void *phi, const void *u, const void *w,
                            int32_t state_fp64, void *grad_phi, double *compliance, void *stream);
 
+/* petto_adjoint without the context's workspace, for callers that cannot
+ * allocate or must not touch allocating calls (code under HIP graph capture,
+ * tight serving loops): same arguments, results and error behaviour as
+ * petto_adjoint (bit-identical outputs), but its partial sums live in one fixed
+ * device array of the library, 2 x 65536 doubles (1 MiB) per GPU, held until
+ * the process ends; the call allocates nothing.  A launch needing more than
+ * 65536 partial-sum slots (one per workgroup: about 1024 x 512 cells per 10,000
+ * slots in 2D, 1.4 M positions per 10,000 in 3D) returns PETTO_ERR_UNSUPPORTED
+ * before any GPU work.  The array is shared by every call on a GPU and keeps
+ * the last call's contents: calls that overlap on one GPU (other streams, other
+ * threads) race on it and must be serialized by the caller.  The array's device
+ * address is resolved at petto_create, so a context must have been created on
+ * the current GPU (else PETTO_ERR_INVALID). */
+petto_status petto_adjoint_noalloc(petto_ctx *ctx, const void *phi, const void *u, const void *w,
+                                   int32_t state_fp64, void *grad_phi, double *compliance, void *stream);
+
 /* Design update in place (normalised sensitivity step, Allen-Cahn step, volume
  * projection).  phi (device) is overwritten; grad_phi (device) is read.  info (host,
  * nprob entries, may be NULL): when given the call waits for the GPU work. */

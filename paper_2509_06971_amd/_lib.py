@@ -95,6 +95,7 @@ def load(path: str = LIB_PATH):
         "petto_apt_solve": (st, [vp, vp, vp, vp, C.POINTER(AptParams), vp, C.POINTER(SolveInfo)]),
         "petto_residual": (st, [vp, vp, vp, vp, vp]),
         "petto_adjoint": (st, [vp, vp, vp, vp, C.c_int32, vp, vp, vp]),
+        "petto_adjoint_noalloc": (st, [vp, vp, vp, vp, C.c_int32, vp, vp, vp]),
         "petto_phase_update": (st, [vp, vp, vp, C.POINTER(PhaseParams), vp, C.POINTER(PhaseInfo)]),
         "petto_step": (st, [vp, vp, vp, vp, vp, vp, C.POINTER(AptParams), C.POINTER(PhaseParams), vp,
                             C.POINTER(SolveInfo), C.POINTER(PhaseInfo)]),

@@ -140,11 +140,14 @@ class Context:
                                         self._ptr(u, self.dtype, self.nstate, "u"),
                                         self._ptr(r, self.dtype, self.nstate, "r"), _stream(stream)))
 
-    def adjoint(self, phi, u, grad, w=None, compliance=None, state_fp64=False, stream=None):
+    def adjoint(self, phi, u, grad, w=None, compliance=None, state_fp64=False, stream=None, noalloc=False):
+        """Compliance and sensitivity (petto_adjoint; noalloc: petto_adjoint_noalloc,
+        whose partial sums live in the library's fixed device array)."""
         sdt = torch.float64 if (state_fp64 or self.prec == L.FP64) else self.dtype
         comp = compliance if compliance is not None else torch.empty(2 * self.nprob, dtype=torch.float64,
                                                                      device="cuda")
-        L.check(self.lib.petto_adjoint(self.h, self._ptr(phi, self.dtype, self.nphase * self.ncell, "phi"),
+        fn = self.lib.petto_adjoint_noalloc if noalloc else self.lib.petto_adjoint
+        L.check(fn(self.h, self._ptr(phi, self.dtype, self.nphase * self.ncell, "phi"),
                                        self._ptr(u, sdt, self.nstate, "u"),
                                        self._ptr(w, sdt, self.nstate, "w") if w is not None else None,
                                        int(bool(state_fp64)),

@@ -10,6 +10,7 @@
 #include <cstring>
 #include <functional>
 #include <map>
+#include <mutex>
 #include <type_traits>
 #include <string>
 #include <algorithm>
@@ -19,6 +20,15 @@
 #include "petto.h"
 
 using namespace petto;
+
+// Partial sums of petto_adjoint_noalloc: a fixed device array (one per GPU, held
+// until the process ends) in place of the context's workspace.  Slots
+// [0, kScratchSlots) take the F.u partials, [kScratchSlots, 2 kScratchSlots) the
+// energy partials.  Host code never passes this name to a kernel: it stands for
+// the array only on the host side; the device address comes from
+// hipGetSymbolAddress (scratch_resolve below).
+constexpr int kScratchSlots = 65536;
+static __device__ __align__(256) double scratch[2 * kScratchSlots];
 
 namespace {
 
@@ -45,6 +55,36 @@ petto_status fail(petto_status s, const char* fmt, ...) {
     petto_status s_ = (expr);              \
     if (s_ < 0) return s_;                 \
   } while (0)
+
+// Device addresses of `scratch`, one per GPU, resolved at context creation with
+// that GPU current.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_addr[kMaxDevices] = {};
+
+petto_status scratch_resolve() {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(PETTO_ERR_UNSUPPORTED, "device %d beyond %d", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_addr[dev] == nullptr) {
+    void* p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (p == nullptr) return fail(PETTO_ERR_HIP, "hipGetSymbolAddress(scratch) returned NULL");
+    g_scratch_addr[dev] = static_cast<double*>(p);
+  }
+  return PETTO_OK;
+}
+
+petto_status scratch_lookup(double** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(PETTO_ERR_UNSUPPORTED, "device %d beyond %d", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  *out = g_scratch_addr[dev];
+  if (*out == nullptr) return fail(PETTO_ERR_INVALID, "no context was created on device %d", dev);
+  return PETTO_OK;
+}
 
 constexpr int kBpd = 256;          // material-kernel blocks per design
 // Rayleigh-quotient blocks per design: about one per 4096 unknowns of the
@@ -850,7 +890,8 @@ petto_status solve_refine(petto_ctx* c, const void* phi, void* u, void* v, const
 
 // Returns the partial-sum slots written (elastic; heat uses the design ranges).
 template <typename U, typename T>
-int adjoint_launch(petto_ctx* c, const void* phi, const void* u, const void* w, void* grad, hipStream_t s) {
+int adjoint_launch(petto_ctx* c, const void* phi, const void* u, const void* w, void* grad, double* pfu, double* pen,
+                   hipStream_t s) {
   const petto_problem& p = c->probs[0];
   if (c->physics == PETTO_ELASTIC) {
     ElAdjoint<U, T> a{};
@@ -859,8 +900,8 @@ int adjoint_launch(petto_ctx* c, const void* phi, const void* u, const void* w, 
     a.phi = static_cast<const T*>(phi);
     a.grad = static_cast<T*>(grad);
     a.F = c->F64;
-    a.partial_fu = c->partial;
-    a.partial_en = c->partial2;
+    a.partial_fu = pfu;
+    a.partial_en = pen;
     a.nphase = c->nphase;
     a.e0 = p.e0;
     a.emin = p.emin;
@@ -877,8 +918,8 @@ int adjoint_launch(petto_ctx* c, const void* phi, const void* u, const void* w, 
     a.des = c->d_des;
     a.tiles = c->heat_lists.at(1).tiles;
     a.dir = c->d_dir;
-    a.partial_fu = c->partial;
-    a.partial_en = c->partial2;
+    a.partial_fu = pfu;
+    a.partial_en = pen;
     a.e0 = p.e0;
     a.emin = p.emin;
     a.p = p.p;
@@ -886,6 +927,27 @@ int adjoint_launch(petto_ctx* c, const void* phi, const void* u, const void* w, 
     launch_heat2d_adjoint<U, T>(a, s);
     return 0;
   }
+}
+
+// Partial-sum slots the sensitivity launch writes (one per workgroup; heat: one
+// per tile of the one-sweep work list).
+int adjoint_slots(const petto_ctx* c) {
+  if (c->physics == PETTO_HEAT) return c->heat_lists.at(1).ntile;
+  return c->ndim == 2 ? el2d_tiles(c->geom) : el3d_adjoint_tiles(c->geom);
+}
+
+// The sensitivity launch and the fixed-order compliance sums, with the partial
+// sums in pfu / pen (each at least adjoint_slots(c) doubles).
+petto_status adjoint_run(petto_ctx* c, const void* phi, const void* u, const void* w, int32_t state_fp64,
+                         void* grad, double* compliance, double* pfu, double* pen, hipStream_t s) {
+  int nt = 0;
+  if (c->prec == PETTO_FP64) nt = adjoint_launch<double, double>(c, phi, u, w, grad, pfu, pen, s);
+  else if (state_fp64) nt = adjoint_launch<double, float>(c, phi, u, w, grad, pfu, pen, s);
+  else nt = adjoint_launch<float, float>(c, phi, u, w, grad, pfu, pen, s);
+  launch_dot_finalize(pfu, pen, c->physics == PETTO_HEAT ? c->d_tile0 : nullptr, nt, c->nprob,
+                      compliance ? compliance : c->comp, s);
+  HIP_TRY(hipGetLastError());
+  return PETTO_OK;
 }
 
 template <typename T>
@@ -1169,6 +1231,8 @@ petto_status petto_create(const petto_problem* probs, int32_t nprob, int32_t pre
     }
   }
   auto build = [&]() -> petto_status {
+    // set-up of the allocation-free sensitivity entry point on this GPU
+    PETTO_TRY(scratch_resolve());
     const size_t es = elem_size(c);
     if (!F.empty()) {
       PETTO_TRY(upload(c, &c->F64, F));
@@ -1460,20 +1524,27 @@ petto_status petto_adjoint(petto_ctx* ctx, const void* phi, const void* u, const
   if (phi == nullptr || u == nullptr || grad_phi == nullptr)
     return fail(PETTO_ERR_INVALID, "phi, u and grad_phi must be non-NULL");
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (ctx->physics == PETTO_ELASTIC) {
-    const int need = ctx->ndim == 2 ? el2d_tiles(ctx->geom) : el3d_adjoint_tiles(ctx->geom);
-    if (need > ctx->ntile)
-      return fail(PETTO_ERR_UNSUPPORTED, "sensitivity launch needs %d partial-sum slots, the context holds %d",
-                  need, ctx->ntile);
-  }
-  int nt = 0;
-  if (ctx->prec == PETTO_FP64) nt = adjoint_launch<double, double>(ctx, phi, u, w, grad_phi, s);
-  else if (state_fp64) nt = adjoint_launch<double, float>(ctx, phi, u, w, grad_phi, s);
-  else nt = adjoint_launch<float, float>(ctx, phi, u, w, grad_phi, s);
-  launch_dot_finalize(ctx->partial, ctx->partial2, ctx->physics == PETTO_HEAT ? ctx->d_tile0 : nullptr, nt,
-                      ctx->nprob, compliance ? compliance : ctx->comp, s);
-  HIP_TRY(hipGetLastError());
-  return PETTO_OK;
+  const int need = adjoint_slots(ctx);
+  if (need > ctx->ntile)
+    return fail(PETTO_ERR_UNSUPPORTED, "sensitivity launch needs %d partial-sum slots, the context holds %d",
+                need, ctx->ntile);
+  return adjoint_run(ctx, phi, u, w, state_fp64, grad_phi, compliance, ctx->partial, ctx->partial2, s);
+}
+
+petto_status petto_adjoint_noalloc(petto_ctx* ctx, const void* phi, const void* u, const void* w,
+                                   int32_t state_fp64, void* grad_phi, double* compliance, void* stream) {
+  g_err.clear();
+  if (ctx == nullptr) return fail(PETTO_ERR_INVALID, "ctx is NULL");
+  if (phi == nullptr || u == nullptr || grad_phi == nullptr)
+    return fail(PETTO_ERR_INVALID, "phi, u and grad_phi must be non-NULL");
+  const int need = adjoint_slots(ctx);
+  if (need > kScratchSlots)
+    return fail(PETTO_ERR_UNSUPPORTED, "sensitivity launch needs %d partial-sum slots, the fixed scratch holds %d",
+                need, kScratchSlots);
+  double* sp = nullptr;
+  PETTO_TRY(scratch_lookup(&sp));
+  return adjoint_run(ctx, phi, u, w, state_fp64, grad_phi, compliance, sp, sp + kScratchSlots,
+                     static_cast<hipStream_t>(stream));
 }
 
 petto_status petto_phase_update(petto_ctx* ctx, void* phi, const void* grad_phi, const petto_phase_params* pp,

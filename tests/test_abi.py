@@ -71,6 +71,7 @@ def test_null_and_count_arguments(lib):
     assert lib.petto_apt_solve(None, None, None, None, None, None, info) == L.ERR_INVALID
     assert lib.petto_residual(None, None, None, None, None) == L.ERR_INVALID
     assert lib.petto_adjoint(None, None, None, None, 0, None, None, None) == L.ERR_INVALID
+    assert lib.petto_adjoint_noalloc(None, None, None, None, 0, None, None, None) == L.ERR_INVALID
     assert lib.petto_phase_update(None, None, None, None, None, None) == L.ERR_INVALID
     assert lib.petto_step(None, None, None, None, None, None, None, None, None, None, None) == L.ERR_INVALID
     assert lib.petto_set_timing(None, 1) == L.ERR_INVALID
