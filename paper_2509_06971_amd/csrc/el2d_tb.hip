@@ -2,13 +2,20 @@
 //
 // A workgroup stages an EX x EY window of grid positions (state, velocity,
 // right-hand side, moduli) once, runs K sweeps on it with the state held in
-// registers and exchanged through LDS, and writes back the inner
-// (EX-2K) x (EY-2K) positions, whose K-step dependency cone lies inside the
-// window.  Each sweep: (B) every position forms its cell's normal stresses and its
-// vertex's shear stress from the LDS state, (C) every unknown takes the stress
-// jumps around it (Eqs. 3.6, 3.9) and the damped update of Eq. 3.12.  The
-// arithmetic is the one of the one-sweep kernel (el2d_ops.hpp), so results are
-// bit-identical for every K.  Per-sweep global traffic drops by about K times.
+// registers, and writes back the inner (EX-2K) x (EY-2K) positions, whose K-step
+// dependency cone lies inside the window.  Each sweep: (B) every position forms
+// its cell's normal stresses and its vertex's shear stress, (C) every unknown
+// takes the stress jumps around it (Eqs. 3.6, 3.9) and the damped update of
+// Eq. 3.12.  The arithmetic is the one of the one-sweep kernel (el2d_ops.hpp),
+// so results are bit-identical for every K.  Per-sweep global traffic drops by
+// about K times.
+//
+// Data movement inside the window: a wave owns RPW consecutive window rows, one
+// position per lane and row.  Neighbours along x are the adjacent lanes (DPP
+// wave shifts, no memory); neighbours along y inside the wave's rows are the
+// thread's own registers; only each wave's first and last rows cross to the
+// neighbouring waves, through small LDS row buffers (two stores and two loads
+// per thread and phase).
 #include "el2d_ops.hpp"
 #include "kernels.hpp"
 
@@ -18,20 +25,40 @@ namespace petto {
 namespace {
 
 constexpr int EX = 64, EY = 32;          // window of positions
-constexpr int NT = 512;                   // threads: 8 waves, one 64-wide row each
-constexpr int RSTEP = NT / EX;            // rows between a thread's positions
-constexpr int PPT = EY / RSTEP;           // positions per thread
-constexpr int PX = EX + 2, PY = EY + 2;   // LDS arrays carry a one-position pad ring
+constexpr int NT = 512;                   // threads
+constexpr int NW = NT / kWave;            // waves (8)
+constexpr int RPW = EY / NW;              // consecutive window rows per wave (4)
+static_assert(EX == kWave && RPW * NW == EY, "one lane per window column, whole rows per wave");
 
+// Rows exchanged between waves: slot w + 1 holds wave w's row; slots 0 and NW + 1
+// (below the window and above it) stay zero, like the zero ring around the window.
 template <typename T>
 struct TbSmem {
-  T dx[PY][PX];
-  T dy[PY][PX];
-  T sxx[PY][PX];                          // cell modulus while staging
-  T syy[PY][PX];
-  T tau[PY][PX];
-  double red[NT / kWave];
+  T ux_last[NW + 2][EX];                  // u_x of each wave's last row
+  T uy_first[NW + 2][EX];                 // u_y of each wave's first row
+  T syy_last[NW + 2][EX];                 // sigma_yy of each wave's last row
+  T tau_first[NW + 2][EX];                // shear stress of each wave's first row
+  T e_last[NW + 2][EX];                   // cell modulus of each wave's last row (staging)
+  double red[NW];
 };
+
+// Value of the lane one to the left (lane - 1) or right (lane + 1) in the wave;
+// the lane at the wave's edge receives zero (the zero ring around the window).
+template <int CTRL, typename T>
+__device__ __forceinline__ T wave_shift(T x) {
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(T, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), CTRL, 0xf, 0xf, false));
+  } else {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xf, 0xf, false);
+    return __builtin_bit_cast(T, ((unsigned long long)(unsigned)hi << 32) | (unsigned long long)(unsigned)lo);
+  }
+}
+template <typename T>
+__device__ __forceinline__ T from_left(T x) { return wave_shift<0x138>(x); }   // wave_shr:1
+template <typename T>
+__device__ __forceinline__ T from_right(T x) { return wave_shift<0x130>(x); }  // wave_shl:1
 
 __device__ __forceinline__ bool pinned_tb(const uint32_t* pins, long k) {
   return pins != nullptr && ((pins[k >> 5] >> (k & 31)) & 1u);
@@ -40,30 +67,39 @@ __device__ __forceinline__ bool pinned_tb(const uint32_t* pins, long k) {
 // K sweeps on the staged window.  Sweep k only forms the stresses of rows
 // [k, EY-k) and updates rows [k+1, EY-k-1): the values outside lie beyond the
 // dependency cone of the written inner rows [K, EY-K), so skipping them leaves
-// those rows unchanged (a row is one wave, so the skip is wave-uniform).  FAST:
-// the window is inside the grid with no pins (no ghosts, every unknown free).
+// those rows unchanged (a row lies in one wave, so the skip is wave-uniform).
+// FAST: the window is inside the grid with no pins (no ghosts, every unknown free).
 template <typename T, int K, bool CHECK, bool FAST>
-__device__ __forceinline__ void tb_sweeps(const ElGeom& g, TbSmem<T>& sm, T (&ux)[PPT], T (&uy)[PPT], T (&vx)[PPT],
-                                          T (&vy)[PPT], const T (&bx)[PPT], const T (&by)[PPT], const T (&lam)[PPT],
-                                          const T (&mu2)[PPT], const T (&mue)[PPT], const T (&fx)[PPT],
-                                          const T (&fy)[PPT], int i, int li, int lw, int c, int je, T rh, T h, T ca,
-                                          T cc, T dt, double& acc) {
+__device__ __forceinline__ void tb_sweeps(const ElGeom& g, TbSmem<T>& sm, T (&ux)[RPW], T (&uy)[RPW], T (&vx)[RPW],
+                                          T (&vy)[RPW], const T (&bx)[RPW], const T (&by)[RPW], const T (&lam)[RPW],
+                                          const T (&mu2)[RPW], const T (&mue)[RPW], const T (&fx)[RPW],
+                                          const T (&fy)[RPW], int i, int li, int w, int je, T rh, T h, T ca, T cc,
+                                          T dt, double& acc) {
   const int nx = g.nx, ny = g.ny;
   // reflected-ghost multipliers of clamped sides (0 on other sides), applied on the
   // first / last row and column of the grid
   const T gb = g.clamp[2] ? T(-1) : T(0), gt = g.clamp[3] ? T(-1) : T(0);
   const T gl = g.clamp[0] ? T(-1) : T(0), gr = g.clamp[1] ? T(-1) : T(0);
+  const int l0 = w * RPW;                 // first window row of this wave
+  // rows skipped by a sweep keep their last stresses; none is read for a kept
+  // result, and the zero start keeps every lane shift well defined
+  T sxx[RPW], syy[RPW], tau[RPW];
+#pragma unroll
+  for (int s = 0; s < RPW; ++s) sxx[s] = syy[s] = tau[s] = T(0);
   for (int k = 0; k < K; ++k) {
     // (B) stresses of the cell and the vertex at every position of rows [k, EY-k)
+    const T ux_prev = sm.ux_last[w][li];          // row l0 - 1
+    const T uy_next = sm.uy_first[w + 2][li];     // row l0 + RPW
 #pragma unroll
-    for (int s = 0; s < PPT; ++s) {
-      const int lj = lw + s * RSTEP, j = je + lj, r = lj + 1;
+    for (int s = 0; s < RPW; ++s) {
+      const int lj = l0 + s, j = je + lj;
+      // x neighbours are lane shifts, so every lane of the wave takes part
+      const T ux_r = from_right(ux[s]);
+      const T uy_lf = from_left(uy[s]);
       if (lj < k || lj >= EY - k) continue;
       const T uxs = ux[s], uys = uy[s];
-      const T ux_r = sm.dx[r][c + 1];
-      const T uy_u = sm.dy[r + 1][c];
-      const T ux_dn = sm.dx[r - 1][c];
-      const T uy_lf = sm.dy[r][c - 1];
+      const T uy_u = s + 1 < RPW ? uy[s + 1 < RPW ? s + 1 : s] : uy_next;
+      const T ux_dn = s > 0 ? ux[s > 0 ? s - 1 : 0] : ux_prev;
       T ux_below = ux_dn, uy_left = uy_lf, ux_here = uxs, uy_here = uys;
       if (!FAST) {
         // reflected ghosts of clamped sides, as the one-sweep kernel stages them
@@ -74,18 +110,26 @@ __device__ __forceinline__ void tb_sweeps(const ElGeom& g, TbSmem<T>& sm, T (&ux
       }
       const T exx = (ux_r - uxs) * rh;
       const T eyy = (uy_u - uys) * rh;
-      el2d::normal_stress<T>(lam[s], mu2[s], exx, eyy, sm.sxx[r][c], sm.syy[r][c]);
-      sm.tau[r][c] = mue[s] * el2d::shear_strain<T>(ux_here, ux_below, uy_here, uy_left, rh);
+      el2d::normal_stress<T>(lam[s], mu2[s], exx, eyy, sxx[s], syy[s]);
+      tau[s] = mue[s] * el2d::shear_strain<T>(ux_here, ux_below, uy_here, uy_left, rh);
     }
+    sm.syy_last[w + 1][li] = syy[RPW - 1];
+    sm.tau_first[w + 1][li] = tau[0];
     __syncthreads();
     // (C) residuals and the damped update of every free unknown of rows [k+1, EY-k-1)
+    const T syy_prev = sm.syy_last[w][li];
+    const T tau_next = sm.tau_first[w + 2][li];
 #pragma unroll
-    for (int s = 0; s < PPT; ++s) {
-      const int lj = lw + s * RSTEP, r = lj + 1;
+    for (int s = 0; s < RPW; ++s) {
+      const int lj = l0 + s;
+      const T sxx_lf = from_left(sxx[s]);
+      const T tau_r = from_right(tau[s]);
       if (lj < k + 1 || lj >= EY - k - 1) continue;
-      const T t0 = sm.tau[r][c];
-      const T rx = el2d::residual<T>(bx[s], h, sm.sxx[r][c], sm.sxx[r][c - 1], sm.tau[r + 1][c], t0);
-      const T ry = el2d::residual<T>(by[s], h, sm.syy[r][c], sm.syy[r - 1][c], sm.tau[r][c + 1], t0);
+      const T t0 = tau[s];
+      const T tau_u = s + 1 < RPW ? tau[s + 1 < RPW ? s + 1 : s] : tau_next;
+      const T syy_dn = s > 0 ? syy[s > 0 ? s - 1 : 0] : syy_prev;
+      const T rx = el2d::residual<T>(bx[s], h, sxx[s], sxx_lf, tau_u, t0);
+      const T ry = el2d::residual<T>(by[s], h, syy[s], syy_dn, tau_r, t0);
       T ux2 = ux[s], vx2 = vx[s], uy2 = uy[s], vy2 = vy[s];
       el2d::update<T>(ca, cc, dt, rx, ux2, vx2);
       el2d::update<T>(ca, cc, dt, ry, uy2, vy2);
@@ -100,16 +144,13 @@ __device__ __forceinline__ void tb_sweeps(const ElGeom& g, TbSmem<T>& sm, T (&ux
         const double ry2 = (inner && fry) ? (double)ry * (double)ry : 0.0;
         acc += rx2 + ry2;
       }
-      sm.dx[r][c] = ux[s];
-      sm.dy[r][c] = uy[s];
     }
+    sm.ux_last[w + 1][li] = ux[RPW - 1];
+    sm.uy_first[w + 1][li] = uy[0];
     __syncthreads();
   }
 }
 
-// Window position (li, lj) lives at LDS [lj + 1][li + 1]; the pad ring stays zero,
-// so neighbour reads need no guards (edge results are outside the written inner
-// region anyway).
 template <typename T, int K, bool CHECK>
 __global__ __launch_bounds__(NT) void el2d_tb_kernel(ElGeom g, ElSweep<T> A, int tiles_x, int ntiles) {
   static_assert(EX - 2 * K > 0 && EY - 2 * K > 0, "window too small for K sweeps");
@@ -122,30 +163,29 @@ __global__ __launch_bounds__(NT) void el2d_tb_kernel(ElGeom g, ElSweep<T> A, int
   const int tile = xcd_tile(blockIdx.x, ntiles);
   const int tyi = tile / tiles_x, txi = tile - tyi * tiles_x;
   const int ie = txi * TXI - K, je = tyi * TYI - K;     // window origin
-  // one window row per wave: the row index is wave-uniform (scalar branches)
-  const int li = threadIdx.x % EX, lw = __builtin_amdgcn_readfirstlane(threadIdx.x / EX);
+  // lane = window column; the wave index is wave-uniform (scalar branches)
+  const int li = threadIdx.x % EX, w = __builtin_amdgcn_readfirstlane(threadIdx.x / EX);
+  const int l0 = w * RPW;
   const int nx = g.nx, ny = g.ny, px = g.px;
   const long pl = g.plane;
   const int i = ie + li;
-  const int c = li + 1;                                  // LDS column
 
-  // zero the pad ring (rows 0 and PY-1, columns 0 and PX-1) of every array
-  for (int q = threadIdx.x; q < 2 * PX + 2 * EY; q += NT) {
-    int r, cc;
-    if (q < 2 * PX) { r = q < PX ? 0 : PY - 1; cc = q % PX; }
-    else { const int t = q - 2 * PX; r = 1 + t / 2; cc = (t & 1) ? PX - 1 : 0; }
-    sm.dx[r][cc] = T(0);
-    sm.dy[r][cc] = T(0);
-    sm.sxx[r][cc] = T(0);
-    sm.syy[r][cc] = T(0);
-    sm.tau[r][cc] = T(0);
+  // the rows below and above the window are zero
+  if (w == 0) {
+    sm.ux_last[0][li] = T(0);
+    sm.syy_last[0][li] = T(0);
+    sm.e_last[0][li] = T(0);
+  }
+  if (w == NW - 1) {
+    sm.uy_first[NW + 1][li] = T(0);
+    sm.tau_first[NW + 1][li] = T(0);
   }
 
-  T ux[PPT], uy[PPT], vx[PPT], vy[PPT], bx[PPT], by[PPT], lam[PPT], mu2[PPT], mue[PPT];
-  T fx[PPT], fy[PPT];                       // 1 for a free unknown, 0 otherwise
+  T ux[RPW], uy[RPW], vx[RPW], vy[RPW], bx[RPW], by[RPW], lam[RPW], mu2[RPW], mue[RPW], e[RPW];
+  T fx[RPW], fy[RPW];                       // 1 for a free unknown, 0 otherwise
 #pragma unroll
-  for (int s = 0; s < PPT; ++s) {
-    const int lj = lw + s * RSTEP, j = je + lj;
+  for (int s = 0; s < RPW; ++s) {
+    const int j = je + l0 + s;
     const bool validx = i >= 0 && i <= nx && j >= 0 && j < ny;
     const bool validy = i >= 0 && i < nx && j >= 0 && j <= ny;
     const long p = (long)j * px + i;
@@ -166,27 +206,33 @@ __global__ __launch_bounds__(NT) void el2d_tb_kernel(ElGeom g, ElSweep<T> A, int
       fy[s] = fix ? T(0) : T(1);
     }
     const bool cell = i >= 0 && i < nx && j >= 0 && j < ny;
-    sm.sxx[lj + 1][c] = cell ? A.E[(long)j * nx + i] : T(0);
-    sm.dx[lj + 1][c] = ux[s];
-    sm.dy[lj + 1][c] = uy[s];
+    e[s] = cell ? A.E[(long)j * nx + i] : T(0);
   }
+  sm.e_last[w + 1][li] = e[RPW - 1];
+  sm.ux_last[w + 1][li] = ux[RPW - 1];
+  sm.uy_first[w + 1][li] = uy[0];
   if (done) return;   // uniform over the workgroup, before its first barrier
   __syncthreads();
   const T lam0 = T(g.lam0), mu0 = T(g.mu0);
+  {
+    const T e_prev = sm.e_last[w][li];                 // cells of row l0 - 1
 #pragma unroll
-  for (int s = 0; s < PPT; ++s) {
-    const int lj = lw + s * RSTEP, j = je + lj, r = lj + 1;
-    const T e = sm.sxx[r][c];
-    lam[s] = e * lam0;
-    mu2[s] = T(2) * (e * mu0);
-    bool act = i >= 0 && j >= 0 && i <= nx && j <= ny, on = false;
-    if (i == 0) { act = act && g.clamp[0]; on = true; }
-    if (i == nx) { act = act && g.clamp[1]; on = true; }
-    if (j == 0) { act = act && g.clamp[2]; on = true; }
-    if (j == ny) { act = act && g.clamp[3]; on = true; }
-    mue[s] = el2d::vertex_modulus<T>(mu0, sm.sxx[r - 1][c - 1], sm.sxx[r - 1][c], sm.sxx[r][c - 1], e, act, on);
+    for (int s = 0; s < RPW; ++s) {
+      const int j = je + l0 + s;
+      const T es = e[s];
+      const T ed = s > 0 ? e[s > 0 ? s - 1 : 0] : e_prev;   // cell below
+      const T e_lf = from_left(es);                          // cell to the left
+      const T ed_lf = from_left(ed);                         // cell below-left
+      lam[s] = es * lam0;
+      mu2[s] = T(2) * (es * mu0);
+      bool act = i >= 0 && j >= 0 && i <= nx && j <= ny, on = false;
+      if (i == 0) { act = act && g.clamp[0]; on = true; }
+      if (i == nx) { act = act && g.clamp[1]; on = true; }
+      if (j == 0) { act = act && g.clamp[2]; on = true; }
+      if (j == ny) { act = act && g.clamp[3]; on = true; }
+      mue[s] = el2d::vertex_modulus<T>(mu0, ed_lf, ed, e_lf, es, act, on);
+    }
   }
-  __syncthreads();
 
   const T rh = T(1.0 / g.h), h = T(g.h);
   // A window that lies strictly inside the grid and holds no pinned unknown has
@@ -194,16 +240,16 @@ __global__ __launch_bounds__(NT) void el2d_tb_kernel(ElGeom g, ElSweep<T> A, int
   const bool inner_window = ie >= 1 && je >= 1 && ie + EX <= nx && je + EY <= ny && g.pins == nullptr;
   double acc = 0.0;
   if (inner_window) {
-    tb_sweeps<T, K, CHECK, true>(g, sm, ux, uy, vx, vy, bx, by, lam, mu2, mue, fx, fy, i, li, lw, c, je, rh, h, ca, cc,
+    tb_sweeps<T, K, CHECK, true>(g, sm, ux, uy, vx, vy, bx, by, lam, mu2, mue, fx, fy, i, li, w, je, rh, h, ca, cc,
                                  dt, acc);
   } else {
-    tb_sweeps<T, K, CHECK, false>(g, sm, ux, uy, vx, vy, bx, by, lam, mu2, mue, fx, fy, i, li, lw, c, je, rh, h, ca,
-                                  cc, dt, acc);
+    tb_sweeps<T, K, CHECK, false>(g, sm, ux, uy, vx, vy, bx, by, lam, mu2, mue, fx, fy, i, li, w, je, rh, h, ca, cc,
+                                  dt, acc);
   }
   // write back the inner positions (padding slots of the grid get zero)
 #pragma unroll
-  for (int s = 0; s < PPT; ++s) {
-    const int lj = lw + s * RSTEP, j = je + lj;
+  for (int s = 0; s < RPW; ++s) {
+    const int lj = l0 + s, j = je + lj;
     if (li < K || li >= EX - K || lj < K || lj >= EY - K) continue;
     if (i > nx || j > ny) continue;
     const long p = (long)j * px + i;
