@@ -277,26 +277,27 @@ petto_status petto_set_timing(petto_ctx *ctx, int32_t on);
 /* Sweeps per launch of the 2D relaxations (elastic and heat).  k in {2, 4, 5, 8, 10}
  * (FP64: {2, 4, 5}): each launch stages an LDS window of the grid and runs k sweeps
  * on it (results bit-identical to one sweep per launch); k = 1: one sweep per
- * launch; k = 0 (default for FP32 contexts): time the candidates on the first
- * solve and keep the fastest.  A block of check_every sweeps uses k only when
- * check_every is a multiple of 2k, else one sweep per launch.  FP64 contexts
- * default to 1; 3D contexts stream along z with one sweep per launch (tiling:
- * petto_set_tile3d). */
+ * launch; k = 0 (the default, FP32 and FP64): the first solve times every
+ * candidate that divides its check blocks on workspace buffers and keeps the
+ * fastest; the choice is cached for the process per (physics, dimension,
+ * precision, check interval, compute units, grid sizes), so later contexts of
+ * the same shape reuse it.  A block of check_every sweeps uses k only when
+ * check_every is a multiple of 2k, else one sweep per launch.  3D contexts
+ * stream along z with one sweep per launch (tiling: petto_set_tile3d). */
 petto_status petto_set_blocking(petto_ctx *ctx, int32_t k);
 
-/* The sweeps per launch in use (0: not chosen yet). */
+/* The sweeps per launch in use (0: not timed yet). */
 int32_t petto_blocking(const petto_ctx *ctx);
 
 /* Tiling of the 3D elastic sweeps (streamed along z, Eqs. 3.6 and 3.12 in 3D):
  * t = 1: columns of 64 x 8 positions through 16 layers (FP64: 64 x 4 through 8),
  * the fewest halo bytes; t = 2: columns of 64 x 4 positions through 4 layers and t = 3:
- * through 2 layers, more workgroups for small grids; t = 0: choose as at
- * creation (t = 1 when it gives at least two workgroups per compute unit, else
- * whichever of t = 2 and t = 3 needs fewer rounds of resident workgroups times
- * staged planes per workgroup).  Results are bit-identical for all tilings
- * except the order of the FP64 residual-norm sum.  Errors: PETTO_ERR_INVALID for
- * other values or a context that is not 3D elastic.  Cached launch graphs are
- * dropped. */
+ * through 2 layers, more workgroups for small grids; t = 0 (the default): the first
+ * solve times the three on workspace buffers and keeps the fastest (cached per
+ * shape like the sweeps per launch; until then a model of resident workgroups
+ * picks one).  Results are bit-identical for all tilings except the order of the
+ * FP64 residual-norm sum.  Errors: PETTO_ERR_INVALID for other values or a context
+ * that is not 3D elastic.  Cached launch graphs are dropped. */
 petto_status petto_set_tile3d(petto_ctx *ctx, int32_t t);
 
 /* The 3D tiling in use (1, 2 or 3; 0 for a NULL context). */

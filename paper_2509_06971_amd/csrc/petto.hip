@@ -164,7 +164,11 @@ struct petto_ctx {
   hipEvent_t ev_beg[kRing] = {};
   bool events = false;
   std::vector<GraphEntry> graphs;
-  int blocking = 0;                    // sweeps per launch (2D elastic); 0: tune on first solve
+  int blocking = 0;                    // sweeps per launch (2D); 0: tune on the first solve
+  bool tuned3d = false;                // 3D tiling timed (or set by the caller)
+  void* tune_a = nullptr;              // FP64 contexts: state, partner and right-hand side for timing
+  void* tune_b = nullptr;
+  void* tune_c = nullptr;
   int ncu = 256;                       // compute units of the device (3D tiling choice)
   SolveState* st_t = nullptr;          // running copy of st for kernel timing (done = 0)
   bool timing = false;
@@ -671,51 +675,135 @@ petto_status status_of(const std::vector<SolveState>& h) {
 // sweep coefficients, time each candidate on workspace buffers (the caller's
 // state is untouched) and keep the fastest per swept cell.  Results do not depend
 // on the choice (all candidates are bit-identical).
-petto_status ensure_blocking(petto_ctx* c, hipStream_t s, int nchk) {
-  if (c->blocking != 0) return PETTO_OK;
-  if (c->ndim != 2 || c->prec != PETTO_FP32) {
-    c->blocking = 1;
-    return PETTO_OK;
+// ------------------------------------------------------------------------------ launch autotuner
+//
+// On the first solve of a context the launch choices that leave results
+// unchanged are timed on workspace buffers and the fastest kept: the sweeps per
+// launch of the 2D relaxations (elastic and heat, FP32 and FP64) and the tiling
+// of the 3D sweep.  Choices are cached for the process per (physics, dimension,
+// precision, check interval, compute units, grid sizes of every design), so a
+// new context of the same shape skips the timing.
+
+struct TuneChoice {
+  int blocking = 0;
+  int tile3d = 0;
+};
+std::mutex g_tune_mu;
+std::map<std::vector<long>, TuneChoice> g_tune_cache;
+
+std::vector<long> tune_key(const petto_ctx* c, int nchk) {
+  std::vector<long> k = {c->physics, c->ndim, c->prec, nchk, c->ncu, c->nprob};
+  for (const petto_problem& p : c->probs) {
+    k.push_back(p.n[0]);
+    k.push_back(p.n[1]);
+    k.push_back(c->ndim == 3 ? p.n[2] : 1);
   }
-  PETTO_TRY(ensure_events(c));
-  float* u = c->d32a;
-  float* ua = c->d32b;
-  float* v = static_cast<float*>(c->ualt);
-  launch_fill<float>(u, c->nstate, 0.f, s);
-  launch_fill<float>(v, c->nstate, 0.f, s);
-  launch_fill<float>(c->b32, c->nstate, 0.f, s);
-  const float* E = static_cast<const float*>(c->E);
-  const int cand[] = {1, 2, 4, 5, 8, 10};
-  double best = 1e300;
-  int best_k = 1;
-  const int saved = c->blocking;
-  for (int k : cand) {
-    if (nchk % (2 * k) != 0) continue;
-    c->blocking = k;
-    const int reps = 40 / k < 4 ? 4 : 40 / k;
-    auto run = [&](int n) {
-      if (c->physics == PETTO_ELASTIC) {
-        for (int q = 0; q < n; ++q) elastic_sweeps<float>(c, s, u, ua, v, E, c->b32, c->st, 2 * k);
+  return k;
+}
+
+// Mean milliseconds per sweep of `n` sweeps (after one untimed block of the same
+// size) with the context's current launch choice, from zero state on workspace
+// buffers.
+template <typename T>
+petto_status time_choice(petto_ctx* c, hipStream_t s, T* u, T* ua, T* v, const T* b, int n, double* ms_out) {
+  const T* E = static_cast<const T*>(c->E);
+  launch_fill<T>(u, c->nstate, T(0), s);
+  launch_fill<T>(v, c->nstate, T(0), s);
+  auto run = [&]() {
+    if (c->physics == PETTO_ELASTIC) elastic_sweeps<T>(c, s, u, ua, v, E, b, c->st, n);
+    else heat_sweeps<T>(c, s, u, ua, v, E, nullptr, c->st, n);
+  };
+  run();
+  HIP_TRY(hipEventRecord(c->ev_beg[0], s));
+  run();
+  HIP_TRY(hipEventRecord(c->ev_end[0], s));
+  HIP_TRY(hipEventSynchronize(c->ev_end[0]));
+  HIP_TRY(hipGetLastError());
+  float ms = 0.f;
+  HIP_TRY(hipEventElapsedTime(&ms, c->ev_beg[0], c->ev_end[0]));
+  *ms_out = ms / (double)n;
+  return PETTO_OK;
+}
+
+// Time the candidates of whichever choice is still open (blocking == 0 for 2D,
+// tuned3d false for 3D elastic).  c->st must hold the coefficients of the solve
+// about to run, with its stop flag clear.
+template <typename T>
+petto_status ensure_tuning(petto_ctx* c, hipStream_t s, int nchk) {
+  const bool three = c->physics == PETTO_ELASTIC && c->ndim == 3;
+  if (three ? c->tuned3d : c->blocking != 0) return PETTO_OK;
+  const std::vector<long> key = tune_key(c, nchk);
+  {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) {
+      if (three) {
+        c->geom.tile3d = it->second.tile3d;
+        c->tuned3d = true;
+        destroy_graphs(c);
       } else {
-        for (int q = 0; q < n; ++q) heat_sweeps<float>(c, s, u, ua, v, E, nullptr, c->st, 2 * k);
+        c->blocking = it->second.blocking;
       }
-    };
-    run(1);
-    HIP_TRY(hipEventRecord(c->ev_beg[0], s));
-    run(reps);
-    HIP_TRY(hipEventRecord(c->ev_end[0], s));
-    HIP_TRY(hipEventSynchronize(c->ev_end[0]));
-    float ms = 0.f;
-    HIP_TRY(hipEventElapsedTime(&ms, c->ev_beg[0], c->ev_end[0]));
-    const double per_sweep = ms / (double)(reps * 2 * k);
-    if (per_sweep < best) {
-      best = per_sweep;
-      best_k = k;
+      return PETTO_OK;
     }
   }
-  (void)saved;
-  HIP_TRY(hipGetLastError());
-  c->blocking = best_k;
+  PETTO_TRY(ensure_events(c));
+  T* u;
+  T* ua;
+  T* b;
+  if (std::is_same<T, float>::value) {
+    u = reinterpret_cast<T*>(c->d32a);
+    ua = reinterpret_cast<T*>(c->d32b);
+    b = reinterpret_cast<T*>(c->b32);
+  } else {
+    u = static_cast<T*>(c->tune_a);
+    ua = static_cast<T*>(c->tune_b);
+    b = static_cast<T*>(c->tune_c);
+  }
+  T* v = static_cast<T*>(c->ualt);
+  launch_fill<T>(b, c->nstate, T(0), s);
+  TuneChoice choice;
+  double best = 1e300;
+  if (three) {
+    const int cands[] = {1, 2, 3};
+    for (int t : cands) {
+      c->geom.tile3d = t;
+      double ms = 0.0;
+      PETTO_TRY(time_choice<T>(c, s, u, ua, v, b, 20, &ms));
+      if (ms < best) {
+        best = ms;
+        choice.tile3d = t;
+      }
+    }
+    c->geom.tile3d = choice.tile3d;
+    c->tuned3d = true;
+    destroy_graphs(c);
+  } else {
+    const bool fp64 = c->prec == PETTO_FP64;
+    const int cands32[] = {1, 2, 4, 5, 8, 10};
+    const int cands64[] = {1, 2, 4, 5};
+    const int* cands = fp64 ? cands64 : cands32;
+    const int ncand = fp64 ? 4 : 6;
+    choice.blocking = 1;
+    for (int q = 0; q < ncand; ++q) {
+      const int k = cands[q];
+      if (nchk % (2 * k) != 0) continue;
+      c->blocking = k;
+      double ms = 0.0;
+      // 40 sweeps or at least 4 launches, an even count
+      const int n = (40 / k < 4 ? 4 : (40 / k + 1) / 2 * 2) * k;
+      PETTO_TRY(time_choice<T>(c, s, u, ua, v, b, n, &ms));
+      if (ms < best) {
+        best = ms;
+        choice.blocking = k;
+      }
+    }
+    c->blocking = choice.blocking;
+  }
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  TuneChoice& slot = g_tune_cache[key];
+  if (three) slot.tile3d = choice.tile3d;
+  else slot.blocking = choice.blocking;
   return PETTO_OK;
 }
 
@@ -734,7 +822,7 @@ petto_status solve_plain(petto_ctx* c, const void* phi, void* u, void* v, const 
   const T* E = static_cast<const T*>(c->E);
   const T* b = static_cast<const T*>(c->Ft);
   const int nchk = ap->check_every;
-  if (std::is_same<T, float>::value) PETTO_TRY(ensure_blocking(c, s, nchk));
+  PETTO_TRY(ensure_tuning<T>(c, s, nchk));
   const bool adapt = ap->adapt != 0;
   // adaptive damping: the residual of the state in u into the free ping-pong
   // buffer, then the Rayleigh-quotient sums
@@ -816,7 +904,7 @@ petto_status solve_refine(petto_ctx* c, const void* phi, void* u, void* v, const
                           hipStream_t s, petto_solve_info* info, bool material_ready) {
   if (!material_ready) PETTO_TRY(material<float>(c, phi, s, true));
   PETTO_TRY(setup(c, s, c->st, ap, ap->tol, 0, ap->max_iter));
-  PETTO_TRY(ensure_blocking(c, s, ap->check_every));
+  PETTO_TRY(ensure_tuning<float>(c, s, ap->check_every));
   double* u64 = static_cast<double*>(u);
   float* v32 = static_cast<float*>(v);
   float* da = c->d32a;
@@ -1292,6 +1380,10 @@ petto_status petto_create(const petto_problem* probs, int32_t nprob, int32_t pre
       PETTO_TRY(dalloc_t(c, &c->d32a, c->nstate));
       PETTO_TRY(dalloc_t(c, &c->d32b, c->nstate));
       PETTO_TRY(dalloc_t(c, &c->b32, c->nstate));
+    } else {
+      PETTO_TRY(dalloc(c, &c->tune_a, c->nstate * es));
+      PETTO_TRY(dalloc(c, &c->tune_b, c->nstate * es));
+      PETTO_TRY(dalloc(c, &c->tune_c, c->nstate * es));
     }
     PETTO_TRY(dalloc_t(c, &c->partial, c->ntile + 64));
     PETTO_TRY(dalloc_t(c, &c->partial2, c->ntile + 64));
@@ -1318,7 +1410,7 @@ petto_status petto_create(const petto_problem* probs, int32_t nprob, int32_t pre
     petto_destroy(c);
     return st;
   }
-  c->blocking = prec == PETTO_FP64 ? 1 : 0;
+  c->blocking = 0;
   *out = c;
   return PETTO_OK;
 }
@@ -1368,7 +1460,6 @@ petto_status petto_set_blocking(petto_ctx* ctx, int32_t k) {
   if (ctx == nullptr) return fail(PETTO_ERR_INVALID, "ctx is NULL");
   const bool ok = k == 0 || k == 1 || k == 2 || k == 4 || k == 5 || (ctx->prec == PETTO_FP32 && (k == 8 || k == 10));
   if (!ok) return fail(PETTO_ERR_INVALID, "unsupported sweeps per launch %d", k);
-  if (k == 0 && ctx->prec == PETTO_FP64) k = 1;
   ctx->blocking = k;
   destroy_graphs(ctx);
   return PETTO_OK;
@@ -1425,6 +1516,7 @@ petto_status petto_set_tile3d(petto_ctx* ctx, int32_t t) {
   if (ctx->physics != PETTO_ELASTIC || ctx->ndim != 3)
     return fail(PETTO_ERR_INVALID, "the 3D tiling applies to 3D elastic contexts");
   if (t < 0 || t > 3) return fail(PETTO_ERR_INVALID, "unsupported 3D tiling %d", t);
+  ctx->tuned3d = t != 0;
   if (t == 0) t = el3d_choose_tiling(ctx->geom, ctx->prec == PETTO_FP64, ctx->ncu);
   ctx->geom.tile3d = t;
   destroy_graphs(ctx);

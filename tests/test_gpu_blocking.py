@@ -97,3 +97,77 @@ def test_heat_batch_blocking_bit_identical(prec, ks):
         res, _ = design.solve(phis[d], p, u0=u0[d], params=design.AptParams(theta=1.0, check_every=80), n_iter=400)
         assert rel_l2(got[o0:o1].reshape(p.cell_shape()), res.u) < (1e-12 if prec == "fp64" else 2e-5), d
     ctx.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+@pytest.mark.parametrize("name", ["cant3d", "multi3d"])
+def test_3d_tilings_bit_identical(name, prec):
+    """Every candidate tiling of the 3D sweep gives the same state and velocity,
+    bit for bit (the norm only up to its summation order)."""
+    require_gpu()
+    prob = {"cant3d": lambda: W.cantilever3d(70, 40, 24), "multi3d": lambda: W.multimaterial3d(64, 20, 18)}[name]()
+    announce(f"3D tilings {name} {prec}")
+    phi = W.random_phi(prob, 6, 0.2, 1.0)
+    u0 = W.random_u(prob, 7, scale=1e-2)
+    dtype = torch.float64 if prec == "fp64" else torch.float32
+    if prec == "fp32":
+        phi = phi.astype(np.float32).astype(np.float64)
+        u0 = u0.astype(np.float32).astype(np.float64)
+    ctx = context(prob, prec)
+    outs = {}
+    for t in (1, 2, 3):
+        ctx.set_tile3d(t)
+        u = dev(u0, dtype)
+        v = ctx.new_state()
+        st, info = ctx.solve(dev(phi, dtype), u, v, theta=1.0, replay_iters=200, check_every=100)
+        assert ctx.tile3d() == t
+        outs[t] = (u.cpu().numpy().copy(), v.cpu().numpy().copy(), info[0]["rel_res"])
+    for t in (2, 3):
+        assert np.array_equal(outs[t][0], outs[1][0]), t
+        assert np.array_equal(outs[t][1], outs[1][1]), t
+        assert outs[t][2] == pytest.approx(outs[1][2], rel=1e-12), t
+    ctx.close()
+
+
+@pytest.mark.parametrize("name,prec", [("cant2d", "fp64"), ("cant2d", "fp32"), ("heat", "fp64"), ("cant3d", "fp32"),
+                                       ("cant3d", "fp64")])
+def test_autotuned_choice_reported_and_cached(name, prec):
+    """The first solve times the launch choices (2D sweeps per launch, 3D tiling)
+    and reports the one kept; a second context of the same shape gets the same
+    choice from the process cache; the state equals that of an explicit choice."""
+    require_gpu()
+    if name == "heat":
+        probs = W.heat_batch_small()[0]
+        prob = probs
+        phi = np.concatenate([x.ravel() for x in W.heat_batch_small()[1]])
+    else:
+        prob = W.cantilever2d(300, 150) if name == "cant2d" else W.cantilever3d(70, 40, 24)
+        phi = W.random_phi(prob, 3, 0.2, 1.0).ravel()
+    announce(f"autotune {name} {prec}")
+    dtype = torch.float64 if prec == "fp64" else torch.float32
+    three = name == "cant3d"
+    choices, states = [], []
+    for rep in range(2):
+        ctx = context(prob, prec)
+        if not three:
+            assert ctx.blocking() == 0          # open until the first solve
+        u, v = ctx.new_state(), ctx.new_state()
+        ctx.solve(dev(phi, dtype), u, v, theta=1.0, replay_iters=200, check_every=100)
+        c = ctx.tile3d() if three else ctx.blocking()
+        allowed = (1, 2, 3) if three else ((1, 2, 4, 5) if prec == "fp64" else (1, 2, 4, 5, 10))
+        assert c in allowed, c
+        choices.append(c)
+        states.append(u.cpu().numpy().copy())
+        ctx.close()
+    assert choices[0] == choices[1]
+    assert np.array_equal(states[0], states[1])
+    # the same solve with one sweep per launch (2D) or the large tiling (3D)
+    ctx = context(prob, prec)
+    if three:
+        ctx.set_tile3d(1)
+    else:
+        ctx.set_blocking(1)
+    u, v = ctx.new_state(), ctx.new_state()
+    ctx.solve(dev(phi, dtype), u, v, theta=1.0, replay_iters=200, check_every=100)
+    assert np.array_equal(u.cpu().numpy(), states[0])
+    ctx.close()

@@ -188,10 +188,9 @@ def test_full_size_sweeps_parity(name, make):
 
 def test_full_size_multimaterial3d_sweeps_parity():
     """The multi-material 3D configuration at full size (256x128x128, 12.8 M
-    unknowns) in the launch configuration the bench times (FP32, the automatic
-    tiling: 64x8 columns through 16 layers, one round of workgroups): 4 sweeps
-    from a random state against 4 FP64 sweeps on the oracle's matrix-free
-    residual, every unknown."""
+    unknowns) in the launch configuration the bench times (FP32, the tiling the
+    first solve times and keeps): 4 sweeps from a random state against 4 FP64
+    sweeps on the oracle's matrix-free residual, every unknown."""
     require_gpu()
     prob = W.multimaterial3d(256, 128, 128)
     announce("full-size sweeps multimaterial3d_256x128x128")
