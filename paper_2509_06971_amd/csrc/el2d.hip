@@ -111,14 +111,12 @@ __global__ __launch_bounds__(kBlock) void el2d_kernel(ElGeom g, ElSweep<T> A, in
   load_tile<T>(g, A.uin, A.E, i0, j0, sm.ux, sm.uy, sm.E);
   __syncthreads();
 
-  const T rh = T(1.0 / g.h);
-  const T h = T(g.h);
   const T lam0 = T(g.lam0), mu0 = T(g.mu0);
   for (int idx = threadIdx.x; idx < (TY + 1) * (TX + 1); idx += kBlock) {
     const int lj = idx / (TX + 1), li = idx - lj * (TX + 1);
     const T e = sm.E[lj][li];
-    const T exx = (sm.ux[lj][li + 1] - sm.ux[lj][li]) * rh;
-    const T eyy = (sm.uy[lj + 1][li] - sm.uy[lj][li]) * rh;
+    const T exx = sm.ux[lj][li + 1] - sm.ux[lj][li];
+    const T eyy = sm.uy[lj + 1][li] - sm.uy[lj][li];
     el2d::normal_stress<T>(e * lam0, T(2) * (e * mu0), exx, eyy, sm.sxx[lj][li], sm.syy[lj][li]);
   }
   for (int idx = threadIdx.x; idx < (TY + 1) * (TX + 1); idx += kBlock) {
@@ -130,7 +128,7 @@ __global__ __launch_bounds__(kBlock) void el2d_kernel(ElGeom g, ElSweep<T> A, in
     // touches is such a reflected tangential one.
     const T mue = el2d::vertex_modulus<T>(mu0, sm.E[lj - 1][li - 1], sm.E[lj - 1][li], sm.E[lj][li - 1],
                                           sm.E[lj][li], act, on);
-    const T gam = el2d::shear_strain<T>(sm.ux[lj][li], sm.ux[lj - 1][li], sm.uy[lj][li], sm.uy[lj][li - 1], rh);
+    const T gam = el2d::shear_strain<T>(sm.ux[lj][li], sm.ux[lj - 1][li], sm.uy[lj][li], sm.uy[lj][li - 1]);
     sm.tau[lj][li] = mue * gam;
   }
   __syncthreads();
@@ -154,7 +152,7 @@ __global__ __launch_bounds__(kBlock) void el2d_kernel(ElGeom g, ElSweep<T> A, in
       const bool fix = (i == 0 && g.fixn[0]) || (i == nx && g.fixn[1]) || pinned(g.pins, p);
       T rx = T(0);
       if (!fix)
-        rx = el2d::residual<T>(bx[r], h, sm.sxx[lj][li], sm.sxx[lj][li - 1], sm.tau[lj + 1][li], sm.tau[lj][li]);
+        rx = el2d::residual<T>(bx[r], sm.sxx[lj][li], sm.sxx[lj][li - 1], sm.tau[lj + 1][li], sm.tau[lj][li]);
       if (MODE == kSweep || MODE == kCheck) {
         T un = sm.ux[lj][li], vn = vx[r];
         if (!fix) el2d::update<T>(ca, cc, dt, rx, un, vn);
@@ -177,7 +175,7 @@ __global__ __launch_bounds__(kBlock) void el2d_kernel(ElGeom g, ElSweep<T> A, in
       const bool fix = (j == 0 && g.fixn[2]) || (j == ny && g.fixn[3]) || pinned(g.pins, q);
       T ry = T(0);
       if (!fix)
-        ry = el2d::residual<T>(by[r], h, sm.syy[lj][li], sm.syy[lj - 1][li], sm.tau[lj][li + 1], sm.tau[lj][li]);
+        ry = el2d::residual<T>(by[r], sm.syy[lj][li], sm.syy[lj - 1][li], sm.tau[lj][li + 1], sm.tau[lj][li]);
       if (MODE == kSweep || MODE == kCheck) {
         T un = sm.uy[lj][li], vn = vy[r];
         if (!fix) el2d::update<T>(ca, cc, dt, ry, un, vn);

@@ -12,18 +12,24 @@ __device__ __forceinline__ T fma_(T a, T b, T c) {
   return fma(a, b, c);
 }
 
-// Normal stresses of a cell from its strains: sigma_aa = lam tr + 2 mu eps_aa (Eq. 3.9).
+// In 2D the face forces do not depend on h: a cell's energy h^2 W(eps) with
+// eps = (difference of u) / h is a quadratic form in the differences alone, so
+// the sweep works with forces (stress times h) formed from displacement
+// differences, and the residual sums their jumps (Eqs. 3.6, 3.9).
+
+// Normal forces of a cell from its displacement differences d_aa = u_a(hi) - u_a(lo):
+// h sigma_aa = lam (d_xx + d_yy) + 2 mu d_aa.
 template <typename T>
-__device__ __forceinline__ void normal_stress(T lam, T mu2, T exx, T eyy, T& sxx, T& syy) {
-  const T lt = lam * (exx + eyy);
-  sxx = fma_(mu2, exx, lt);
-  syy = fma_(mu2, eyy, lt);
+__device__ __forceinline__ void normal_stress(T lam, T mu2, T dxx, T dyy, T& sxx, T& syy) {
+  const T lt = lam * (dxx + dyy);
+  sxx = fma_(mu2, dxx, lt);
+  syy = fma_(mu2, dyy, lt);
 }
 
-// Engineering shear strain of a vertex: (ux - ux_below) / h + (uy - uy_left) / h.
+// Engineering shear displacement of a vertex (h gamma): (ux - ux_below) + (uy - uy_left).
 template <typename T>
-__device__ __forceinline__ T shear_strain(T ux, T ux_below, T uy, T uy_left, T rh) {
-  return fma_(uy - uy_left, rh, (ux - ux_below) * rh);
+__device__ __forceinline__ T shear_strain(T ux, T ux_below, T uy, T uy_left) {
+  return (ux - ux_below) + (uy - uy_left);
 }
 
 // Shear modulus of a vertex for the divergence: mean of the four cells around it
@@ -36,10 +42,10 @@ __device__ __forceinline__ T vertex_modulus(T mu0, T e00, T e10, T e01, T e11, b
   return wall ? T(2) * m : m;
 }
 
-// Residual (force units) of a face unknown: load + h (stress jump) + h (shear jump).
+// Residual (force units) of a face unknown: load + normal-force jump + shear-force jump.
 template <typename T>
-__device__ __forceinline__ T residual(T b, T h, T s_hi, T s_lo, T t_hi, T t_lo) {
-  return fma_(h, t_hi - t_lo, fma_(h, s_hi - s_lo, b));
+__device__ __forceinline__ T residual(T b, T s_hi, T s_lo, T t_hi, T t_lo) {
+  return (b + (s_hi - s_lo)) + (t_hi - t_lo);
 }
 
 // Damped-wave update: v <- a v + c r, u <- u + dt v.

@@ -46,12 +46,13 @@ struct TbSmem {
 // the lane at the wave's edge receives zero (the zero ring around the window).
 template <int CTRL, typename T>
 __device__ __forceinline__ T wave_shift(T x) {
+  // bound control set: a lane whose source lies outside the wave receives zero
   if constexpr (sizeof(T) == 4) {
-    return __builtin_bit_cast(T, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), CTRL, 0xf, 0xf, false));
+    return __builtin_bit_cast(T, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), CTRL, 0xf, 0xf, true));
   } else {
     const unsigned long long b = __builtin_bit_cast(unsigned long long, x);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, 0xf, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xf, 0xf, false);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)b, CTRL, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), CTRL, 0xf, 0xf, true);
     return __builtin_bit_cast(T, ((unsigned long long)(unsigned)hi << 32) | (unsigned long long)(unsigned)lo);
   }
 }
@@ -73,8 +74,8 @@ template <typename T, int K, bool CHECK, bool FAST>
 __device__ __forceinline__ void tb_sweeps(const ElGeom& g, TbSmem<T>& sm, T (&ux)[RPW], T (&uy)[RPW], T (&vx)[RPW],
                                           T (&vy)[RPW], const T (&bx)[RPW], const T (&by)[RPW], const T (&lam)[RPW],
                                           const T (&mu2)[RPW], const T (&mue)[RPW], const T (&fx)[RPW],
-                                          const T (&fy)[RPW], int i, int li, int w, int je, T rh, T h, T ca, T cc,
-                                          T dt, double& acc) {
+                                          const T (&fy)[RPW], int i, int li, int w, int je, T ca, T cc, T dt,
+                                          double& acc) {
   const int nx = g.nx, ny = g.ny;
   // reflected-ghost multipliers of clamped sides (0 on other sides), applied on the
   // first / last row and column of the grid
@@ -108,10 +109,10 @@ __device__ __forceinline__ void tb_sweeps(const ElGeom& g, TbSmem<T>& sm, T (&ux
         ux_here = j == ny ? gt * ux_dn : uxs;
         uy_here = i == nx ? gr * uy_lf : uys;
       }
-      const T exx = (ux_r - uxs) * rh;
-      const T eyy = (uy_u - uys) * rh;
+      const T exx = ux_r - uxs;
+      const T eyy = uy_u - uys;
       el2d::normal_stress<T>(lam[s], mu2[s], exx, eyy, sxx[s], syy[s]);
-      tau[s] = mue[s] * el2d::shear_strain<T>(ux_here, ux_below, uy_here, uy_left, rh);
+      tau[s] = mue[s] * el2d::shear_strain<T>(ux_here, ux_below, uy_here, uy_left);
     }
     sm.syy_last[w + 1][li] = syy[RPW - 1];
     sm.tau_first[w + 1][li] = tau[0];
@@ -128,8 +129,8 @@ __device__ __forceinline__ void tb_sweeps(const ElGeom& g, TbSmem<T>& sm, T (&ux
       const T t0 = tau[s];
       const T tau_u = s + 1 < RPW ? tau[s + 1 < RPW ? s + 1 : s] : tau_next;
       const T syy_dn = s > 0 ? syy[s > 0 ? s - 1 : 0] : syy_prev;
-      const T rx = el2d::residual<T>(bx[s], h, sxx[s], sxx_lf, tau_u, t0);
-      const T ry = el2d::residual<T>(by[s], h, syy[s], syy_dn, tau_r, t0);
+      const T rx = el2d::residual<T>(bx[s], sxx[s], sxx_lf, tau_u, t0);
+      const T ry = el2d::residual<T>(by[s], syy[s], syy_dn, tau_r, t0);
       T ux2 = ux[s], vx2 = vx[s], uy2 = uy[s], vy2 = vy[s];
       el2d::update<T>(ca, cc, dt, rx, ux2, vx2);
       el2d::update<T>(ca, cc, dt, ry, uy2, vy2);
@@ -234,17 +235,16 @@ __global__ __launch_bounds__(NT) void el2d_tb_kernel(ElGeom g, ElSweep<T> A, int
     }
   }
 
-  const T rh = T(1.0 / g.h), h = T(g.h);
   // A window that lies strictly inside the grid and holds no pinned unknown has
   // no ghosts and no fixed unknowns: its sweeps skip those selects.
   const bool inner_window = ie >= 1 && je >= 1 && ie + EX <= nx && je + EY <= ny && g.pins == nullptr;
   double acc = 0.0;
   if (inner_window) {
-    tb_sweeps<T, K, CHECK, true>(g, sm, ux, uy, vx, vy, bx, by, lam, mu2, mue, fx, fy, i, li, w, je, rh, h, ca, cc,
-                                 dt, acc);
+    tb_sweeps<T, K, CHECK, true>(g, sm, ux, uy, vx, vy, bx, by, lam, mu2, mue, fx, fy, i, li, w, je, ca, cc, dt,
+                                 acc);
   } else {
-    tb_sweeps<T, K, CHECK, false>(g, sm, ux, uy, vx, vy, bx, by, lam, mu2, mue, fx, fy, i, li, w, je, rh, h, ca, cc,
-                                  dt, acc);
+    tb_sweeps<T, K, CHECK, false>(g, sm, ux, uy, vx, vy, bx, by, lam, mu2, mue, fx, fy, i, li, w, je, ca, cc, dt,
+                                  acc);
   }
   // write back the inner positions (padding slots of the grid get zero)
 #pragma unroll
