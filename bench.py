@@ -13,8 +13,9 @@ steps), the roofline of the dominant kernel (the FP32 multi-sweep correction
 kernel, timed after the timed steps with HIP events around back-to-back launches
 on the same stream; algorithmic bytes beside the counter-recorded HBM bytes; the
 whole sweep blocks of the timed steps, timed by the library's events, are
-reported beside it), sweep-throughput legs of the 64-design heat batch and of
-the 256 x 128 x 128 multi-material cantilever with their own rooflines, the time
+reported beside it), sweep-throughput legs of the 64-design heat batch, the
+128 x 64 x 64 cantilever and the 256 x 128 x 128 multi-material cantilever with
+their own rooflines, the time
 to converged design (100 design steps, FP32 production mode against FP64 plain),
 and the oracle timed on the host cores on a bounded sample of the same workload.
 """
@@ -80,7 +81,7 @@ def parse():
                     help="time to converged design: the legs to run, of fp32 (refined, graphs, multi-sweep "
                          "launches), fp64 (one sweep per launch, no graphs) and fp64g (FP64 with the same "
                          "graphs and, in 2D, the fastest sweeps per launch)")
-    ap.add_argument("--legs", default="heat_batch64,multimaterial3d_256x128x128",
+    ap.add_argument("--legs", default="heat_batch64,cantilever3d_128x64x64,multimaterial3d_256x128x128",
                     help="default line: sweep-throughput legs of other configurations to append "
                          "(comma-separated workloads; empty for none)")
     ap.add_argument("--line-ttd-steps", type=int, default=100,
@@ -130,7 +131,7 @@ def bytes_per_cell(workload):
 # counter measurement applies only while they are unchanged.
 KERNEL_SOURCES = {"el2d": ["el2d_tb.hip", "el2d.hip", "el2d_ops.hpp"],
                   "heat": ["heat2d_tb.hip", "heat2d.hip", "heat_ops.hpp"],
-                  "el3d": ["el3d_stream.hip", "el3d_ops.hpp"]}
+                  "el3d": ["el3d_stream.hip", "el3d_reg.hip", "el3d_entry.hpp", "el3d_ops.hpp"]}
 
 
 def source_digest(family):
@@ -169,8 +170,12 @@ def kernel_roofline(ctx, ncell, family, workload, refined=False, launches=200):
     elif family == "heat":
         name = f"heat2d_tb_kernel<float, {k}, false>" if k > 1 else "heat2d_kernel<float, 0>"
     else:
-        ty, kz = {1: (8, 16), 2: (4, 4), 3: (4, 2)}[ctx.tile3d()]
-        name = f"el3d_stream_kernel<float, {ty}, {kz}, 0>"
+        t = ctx.tile3d()
+        if t >= 4:
+            name = f"el3d_reg_kernel<8, {32 if t == 4 else 16}, 0>"
+        else:
+            ty, kz = {1: (8, 16), 2: (4, 4), 3: (4, 2)}[t]
+            name = f"el3d_stream_kernel<float, {ty}, {kz}, 0>"
     launch_s = ms * 1e-3
     bpc = BYTES_PER_CELL[family]
     alg = bpc * ncell * k

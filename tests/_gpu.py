@@ -44,7 +44,8 @@ def mixed_elastic(ndim, variant=0):
     """Ragged grid with clamped, roller and free sides and a few extra pins.
     3D variant 1 has n_x a multiple of 64 and a clamped x = n_x side (the face
     column that the 3D tiling hands to the last x-tile); variant 2 is thinner than
-    one tile in y and z and barely over one tile in x, clamped on every side."""
+    one tile in y and z and barely over one tile in x, clamped on every side;
+    variant 3 has n_x a multiple of 64 and n_y of 8, and several z-tiles."""
     if ndim == 2:
         n = (150, 37)
         side = (W.CLAMPED, W.ROLLER, W.FREE, W.CLAMPED, 0, 0)
@@ -54,9 +55,15 @@ def mixed_elastic(ndim, variant=0):
     elif variant == 1:
         n = (64, 7, 11)
         side = (W.FREE, W.CLAMPED, W.CLAMPED, W.ROLLER, W.FREE, W.CLAMPED)
-    else:
+    elif variant == 2:
         n = (66, 3, 2)
         side = (W.CLAMPED,) * 6
+    else:
+        # n_x a multiple of 64 and n_y of 8: the face column and the face row fall
+        # to the halo waves of the register-column 3D sweep (with the corner);
+        # several z-tiles with a short top tile, clamped z sides (ghost layers)
+        n = (128, 16, 35)
+        side = (W.CLAMPED, W.CLAMPED, W.ROLLER, W.CLAMPED, W.CLAMPED, W.CLAMPED)
     fixed = W._side_normal_fixed(ndim, n, side)
     valid = W.dof_valid_mask(ndim, n)
     rng = np.random.default_rng(11)

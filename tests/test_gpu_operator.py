@@ -17,12 +17,15 @@ def _elastic_cases():
     return [("mixed2d", lambda: mixed_elastic(2)), ("mixed3d", lambda: mixed_elastic(3)),
             ("mixed3d64", lambda: mixed_elastic(3, 1)), ("thin3d", lambda: mixed_elastic(3, 2)),
             ("cant2d", lambda: W.cantilever2d(64, 32)), ("cant3d", lambda: W.cantilever3d(20, 8, 6)),
-            ("multi3d", lambda: W.multimaterial3d(24, 10, 8))]
+            ("multi3d", lambda: W.multimaterial3d(24, 10, 8)), ("duty3d", lambda: mixed_elastic(3, 3))]
 
 
-def _tilings(prob):
-    """3D contexts: every sweep tiling; 2D: the default."""
-    return [1, 2, 3] if prob.ndim == 3 else [None]
+def _tilings(prob, prec="fp64"):
+    """3D contexts: every sweep tiling (the register-column tilings 4 and 5 run
+    FP32 sweeps only); 2D: the default."""
+    if prob.ndim != 3:
+        return [None]
+    return [1, 2, 3, 4, 5] if prec == "fp32" else [1, 2, 3]
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
@@ -41,7 +44,7 @@ def test_elastic_residual_parity(name, make, prec):
     E = elastic.modulus(phi, prob)
     want = elastic.residual(u, E, prob, design.load_vector(prob))
     scale = np.abs(elastic.internal_force(np.abs(u), E, prob)).max() + np.abs(want).max()
-    for t in _tilings(prob):
+    for t in _tilings(prob, prec):
         if t is not None:
             ctx.set_tile3d(t)
         r = ctx.new_state()
@@ -83,13 +86,13 @@ def test_heat_batch_residual_parity(prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("name,make", _elastic_cases()[:4] + [("cant2d", lambda: W.cantilever2d(64, 32))])
+@pytest.mark.parametrize("name,make", _elastic_cases()[:4] + _elastic_cases()[4:6] + _elastic_cases()[7:])
 def test_sweeps_parity(name, make, prec):
     """200 damped-wave sweeps from a random state equal the oracle's sweeps (3D:
-    with both sweep tilings)."""
+    with every sweep tiling)."""
     require_gpu()
     prob = make()
-    for t in _tilings(prob):
+    for t in _tilings(prob, prec):
         _sweeps_case(name, prob, prec, t)
 
 
