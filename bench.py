@@ -131,7 +131,7 @@ def bytes_per_cell(workload):
 # counter measurement applies only while they are unchanged.
 KERNEL_SOURCES = {"el2d": ["el2d_tb.hip", "el2d.hip", "el2d_ops.hpp"],
                   "heat": ["heat2d_tb.hip", "heat2d.hip", "heat_ops.hpp"],
-                  "el3d": ["el3d_stream.hip", "el3d_reg.hip", "el3d_entry.hpp", "el3d_ops.hpp"]}
+                  "el3d": ["el3d_stream.hip", "el3d_ops.hpp"]}
 
 
 def source_digest(family):
@@ -170,12 +170,8 @@ def kernel_roofline(ctx, ncell, family, workload, refined=False, launches=200):
     elif family == "heat":
         name = f"heat2d_tb_kernel<float, {k}, false>" if k > 1 else "heat2d_kernel<float, 0>"
     else:
-        t = ctx.tile3d()
-        if t >= 4:
-            name = f"el3d_reg_kernel<8, {32 if t == 4 else 16}, 0>"
-        else:
-            ty, kz = {1: (8, 16), 2: (4, 4), 3: (4, 2)}[t]
-            name = f"el3d_stream_kernel<float, {ty}, {kz}, 0>"
+        ty, kz = {1: (8, 16), 2: (4, 4), 3: (4, 2)}[ctx.tile3d()]
+        name = f"el3d_stream_kernel<float, {ty}, {kz}, 0>"
     launch_s = ms * 1e-3
     bpc = BYTES_PER_CELL[family]
     alg = bpc * ncell * k

@@ -289,25 +289,18 @@ petto_status petto_set_blocking(petto_ctx *ctx, int32_t k);
 /* The sweeps per launch in use (0: not timed yet). */
 int32_t petto_blocking(const petto_ctx *ctx);
 
-/* Tiling of the 3D elastic sweeps (streamed along z, Eqs. 3.6 and 3.12 in 3D).
- * LDS-plane columns, which stage each z-layer with its halo in LDS:
+/* Tiling of the 3D elastic sweeps (streamed along z, Eqs. 3.6 and 3.12 in 3D):
  * t = 1: columns of 64 x 8 positions through 16 layers (FP64: 64 x 4 through 8),
- * the fewest halo bytes; t = 2: columns of 64 x 4 positions through 4 layers and
- * t = 3: through 2 layers, more workgroups for small grids.  Register columns
- * (FP32 contexts only), which keep every value at its own position in registers
- * and exchange only the rows' edges through LDS, one barrier per layer: t = 4:
- * columns of 64 x 8 positions through 32 layers; t = 5: through 16 layers (both
- * run the FP32 sweeps; the FP64 residual of the refined mode and the residual
- * entry point use tiling 1).  t = 0 (the default): the first solve times the
- * candidates on workspace buffers and keeps the fastest (cached per shape like
- * the sweeps per launch; until then a model of resident workgroups picks one of
- * 1-3).  Results are bit-identical for all tilings except the order of the FP64
- * residual-norm sum.  Errors: PETTO_ERR_INVALID for other values, for t = 4 or 5
- * in an FP64 context, or for a context that is not 3D elastic.  Cached launch
- * graphs are dropped. */
+ * the fewest halo bytes; t = 2: columns of 64 x 4 positions through 4 layers and t = 3:
+ * through 2 layers, more workgroups for small grids; t = 0 (the default): the first
+ * solve times the three on workspace buffers and keeps the fastest (cached per
+ * shape like the sweeps per launch; until then a model of resident workgroups
+ * picks one).  Results are bit-identical for all tilings except the order of the
+ * FP64 residual-norm sum.  Errors: PETTO_ERR_INVALID for other values or a context
+ * that is not 3D elastic.  Cached launch graphs are dropped. */
 petto_status petto_set_tile3d(petto_ctx *ctx, int32_t t);
 
-/* The 3D tiling in use (1 to 5; 0 for a NULL context). */
+/* The 3D tiling in use (1, 2 or 3; 0 for a NULL context). */
 int32_t petto_tile3d(const petto_ctx *ctx);
 
 /* Time the context's dominant sweep kernel (the relaxation launch of Eq. 3.12 /

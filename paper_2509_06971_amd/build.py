@@ -18,7 +18,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libpetto.so")
-SOURCES = ["petto.hip", "el2d.hip", "el2d_tb.hip", "el3d.hip", "el3d_stream.hip", "el3d_reg.hip", "heat2d.hip", "heat2d_tb.hip", "control.hip", "phase.hip"]
+SOURCES = ["petto.hip", "el2d.hip", "el2d_tb.hip", "el3d.hip", "el3d_stream.hip", "heat2d.hip", "heat2d_tb.hip", "control.hip", "phase.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -15,7 +15,6 @@
 // Offsets within a layer are 32-bit and relative to each component's array.
 #include <type_traits>
 
-#include "el3d_entry.hpp"
 #include "el3d_ops.hpp"
 #include "kernels.hpp"
 
@@ -45,10 +44,41 @@ __device__ __forceinline__ bool pinned3s(const uint32_t* pins, long k) {
   return pins != nullptr && ((pins[k >> 5] >> (k & 31)) & 1u);
 }
 
-using el3d::Entry;
-using el3d::edge_ok;
-using el3d::ldo;
-using el3d::sto;
+// side activity along one axis for an edge index; sets `on` on a side
+__device__ __forceinline__ bool edge_ok(int idx, int n, int clo, int chi, bool& on) {
+  if (idx == 0) { on = true; return clo != 0; }
+  if (idx == n) { on = true; return chi != 0; }
+  return idx > 0 && idx < n;
+}
+
+// Reflection of a face unknown along one of its foreign axes: +1 inside [0, n),
+// the clamped side's -1 (0 for other sides) one step outside, 0 further out;
+// `src` is the index folded back inside, `ghost` whether idx was outside.
+__device__ __forceinline__ int reflect(int idx, int n, int clo, int chi, int& src, bool& ghost) {
+  ghost = !(idx >= 0 && idx < n);
+  src = idx;
+  if (!ghost) return 1;
+  if (idx == -1) { src = 0; return clo ? -1 : 0; }
+  if (idx == n) { src = n - 1; return chi ? -1 : 0; }
+  src = 0;
+  return 0;
+}
+
+// Element access at a byte offset from a workgroup-uniform base: the address is
+// a scalar base plus a 32-bit vector offset (no per-lane 64-bit arithmetic).
+// (The offset passes through an empty asm so that its zero extension is formed
+// beside the access, where instruction selection can fold it into the
+// scalar-base form, rather than hoisted out of the layer loop as a 64-bit value.)
+template <typename T>
+__device__ __forceinline__ T ldo(const T* __restrict__ base, unsigned off) {
+  asm volatile("" : "+v"(off));
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + off);
+}
+template <typename T>
+__device__ __forceinline__ void sto(T* __restrict__ base, unsigned off, T v) {
+  asm volatile("" : "+v"(off));
+  *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + off) = v;
+}
 
 // Bits of a thread's own-position word.
 enum : unsigned {
@@ -64,14 +94,58 @@ enum : unsigned {
   kXfok = 512u,    // ... where u_x exists
 };
 
-// The staged LDS entry q of a column at (i0, j0): grid position (i0 - 1 + column,
-// j0 - 1 + row) of the (TY + 3) x (TX + 3) plane.
+// What one staged LDS entry needs, worked out once per workgroup.  The
+// multipliers are +1, -1 (reflected ghost of a clamped side) or 0; the edge
+// factors 0 (inactive), 1, or 2 (on a clamped wall), so that multiplying by
+// them is exact.
+template <typename T>
+struct Entry {
+  unsigned ox, oy, oz, oe;  // in-layer byte offsets of the sources (u_x, u_y, u_z, modulus)
+  T mx, my, mz, me;         // multipliers on layers inside [0, nz)
+  T gx, gy;                 // u_x / u_y multipliers on a z-ghost layer (0 at corners)
+  T fxy, fxz, fyz;          // xy-position part of the xy, xz and yz edge factors
+  int q;                    // LDS index (row * LX + column)
+};
+
 template <typename T>
 __device__ __forceinline__ void make_entry(const ElGeom& g, int q, int i0, int j0, Entry<T>& E) {
+  const int nx = g.nx, ny = g.ny;
   const int eb = q / LX;
   const int ea = q - eb * LX;
-  el3d::make_entry_at<T>(g, i0 - 1 + ea, j0 - 1 + eb, E);
   E.q = q;
+  const int i = i0 - 1 + ea, j = j0 - 1 + eb;
+  int si, sj;
+  bool gh_i, gh_j;
+  const int ri = reflect(i, nx, g.clamp[0], g.clamp[1], si, gh_i);
+  const int rj = reflect(j, ny, g.clamp[2], g.clamp[3], sj, gh_j);
+  constexpr unsigned W = sizeof(T);
+  // u_x(i, j): own axis x in [0, nx], foreign axis y
+  const bool own_x = i >= 0 && i <= nx;
+  E.mx = T(own_x ? rj : 0);
+  E.ox = (unsigned)(own_x ? sj * g.px + i : 0) * W;
+  E.gx = gh_j ? T(0) : E.mx;
+  // u_y(i, j): own axis y in [0, ny], foreign axis x
+  const bool own_y = j >= 0 && j <= ny;
+  E.my = T(own_y ? ri : 0);
+  E.oy = (unsigned)(own_y ? j * g.px + si : 0) * W;
+  E.gy = gh_i ? T(0) : E.my;
+  // u_z(i, j): foreign axes x and y; outside on both is a corner (zero)
+  E.mz = T((gh_i && gh_j) ? 0 : ri * rj);
+  E.oz = (unsigned)(sj * g.px + si) * W;
+  // cell modulus
+  const bool me = i >= 0 && i < nx && j >= 0 && j < ny;
+  E.me = T(me ? 1 : 0);
+  E.oe = (unsigned)(me ? j * nx + i : 0) * W;
+  bool on = false;
+  const bool ai = edge_ok(i, nx, g.clamp[0], g.clamp[1], on);
+  const bool aj = edge_ok(j, ny, g.clamp[2], g.clamp[3], on);
+  E.fxy = T((ai && aj) ? (on ? 2 : 1) : 0);
+  bool onx = false;
+  const bool axz = j >= 0 && j < ny && edge_ok(i, nx, g.clamp[0], g.clamp[1], onx);
+  E.fxz = T(axz ? (onx ? 2 : 1) : 0);
+  bool ony = false;
+  const bool ayz = i >= 0 && i < nx && edge_ok(j, ny, g.clamp[2], g.clamp[3], ony);
+  E.fyz = T(ayz ? (ony ? 2 : 1) : 0);
 }
 
 template <typename T, int TY>
@@ -592,14 +666,12 @@ int launch_v(const ElGeom& g, const ElSweep<T>& a, hipStream_t s) {
 
 int el3d_tiles_prec(const ElGeom& g, bool fp64) {
   if (fp64) return g.tile3d == 3 ? count_s<double, 3>(g) : g.tile3d == 2 ? count_s<double, 2>(g) : count_s<double, 1>(g);
-  if (g.tile3d >= 4) return el3d_reg_count(g, g.tile3d);
   return g.tile3d == 3 ? count_s<float, 3>(g) : g.tile3d == 2 ? count_s<float, 2>(g) : count_s<float, 1>(g);
 }
 
 int el3d_tiles(const ElGeom& g) {
-  const int c[8] = {count_s<float, 1>(g),  count_s<float, 2>(g),  count_s<float, 3>(g),
-                    count_s<double, 1>(g), count_s<double, 2>(g), count_s<double, 3>(g),
-                    el3d_reg_count(g, 4),  el3d_reg_count(g, 5)};
+  const int c[6] = {count_s<float, 1>(g),  count_s<float, 2>(g),  count_s<float, 3>(g),
+                    count_s<double, 1>(g), count_s<double, 2>(g), count_s<double, 3>(g)};
   int m = 0;
   for (int x : c) m = x > m ? x : m;
   return m;
@@ -622,11 +694,6 @@ int el3d_choose_tiling(const ElGeom& g, bool fp64, int ncu) {
 
 template <typename T, int MODE>
 int launch_el3d(const ElGeom& g, const ElSweep<T>& a, hipStream_t s) {
-  if constexpr (std::is_same<T, float>::value && (MODE == kSweep || MODE == kCheck)) {
-    // register-column tilings: FP32 sweeps (other modes run the large plane tiling,
-    // which gives the same values)
-    if (g.tile3d >= 4) return launch_el3d_reg<MODE>(g, a, s);
-  }
   if (g.tile3d == 3) return launch_v<T, 3, MODE>(g, a, s);
   return g.tile3d == 2 ? launch_v<T, 2, MODE>(g, a, s) : launch_v<T, 1, MODE>(g, a, s);
 }

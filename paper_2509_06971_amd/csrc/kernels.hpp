@@ -16,7 +16,7 @@ struct ElGeom {
   int clamp[6];             // side is clamped: tangential unknowns reflect, edges active
   int fixn[6];              // side holds the normal unknown at zero (clamped or roller)
   const uint32_t* pins;     // extra Dirichlet unknowns as a bitmask, or nullptr
-  int tile3d;               // 3D sweep tiling: 1-3 LDS-plane columns, 4-5 register columns (FP32)
+  int tile3d;               // 3D sweep tiling: 1 large columns, 2 small columns
 };
 
 template <typename T>
@@ -31,8 +31,6 @@ struct ElSweep {
   const SolveState* st;     // coefficients and stop flag (sweep / check; refine: stop flag or nullptr)
   double* partial;          // per-tile sum of r^2 (check / refine modes)
   float* b32;               // refine: receives float(r)
-  int bk_lo = 0;            // 3D register-column sweep: the right-hand side is read only on
-  int bk_hi = 1 << 30;      // layers [bk_lo, bk_hi] (zero elsewhere; a sparse load)
 };
 
 // Launchers return the number of tiles (= partial-sum slots written).
@@ -48,11 +46,6 @@ template <typename T, int K, bool CHECK>
 int launch_el2d_tb(const ElGeom& g, const ElSweep<T>& a, hipStream_t s);
 int el2d_tb_tiles(const ElGeom& g, int K);   // 0 for an unsupported K
 int el3d_tiles_prec(const ElGeom& g, bool fp64);   // for the tiling g.tile3d
-// Register-column 3D sweep (FP32, sweep and check modes; tilings 4 and 5):
-// bit-identical to the LDS-plane kernel.
-template <int MODE>
-int launch_el3d_reg(const ElGeom& g, const ElSweep<float>& a, hipStream_t s);
-int el3d_reg_count(const ElGeom& g, int t);   // workgroups of tiling t (4 or 5)
 // Tiling for a grid: the large one when it gives at least two workgroups per
 // compute unit, else the shorter-column tiling of the smaller modelled time.
 int el3d_choose_tiling(const ElGeom& g, bool fp64, int ncu);

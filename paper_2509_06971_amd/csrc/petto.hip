@@ -166,8 +166,6 @@ struct petto_ctx {
   std::vector<GraphEntry> graphs;
   int blocking = 0;                    // sweeps per launch (2D); 0: tune on the first solve
   bool tuned3d = false;                // 3D tiling timed (or set by the caller)
-  int load_k0 = 1 << 30, load_k1 = -1; // 3D: z-layers holding a nonzero load
-  bool last_refine = false;            // the last solve ran the refined mode
   void* tune_a = nullptr;              // FP64 contexts: state, partner and right-hand side for timing
   void* tune_b = nullptr;
   void* tune_c = nullptr;
@@ -529,10 +527,6 @@ int elastic_sweeps(const petto_ctx* c, hipStream_t s, T* u, T* ualt, T* v, const
   a.b = b;
   a.st = st;
   a.partial = c->partial;
-  if (c->ndim == 3 && static_cast<const void*>(b) == c->Ft) {
-    a.bk_lo = c->load_k0;
-    a.bk_hi = c->load_k1;
-  }
   const int k = block_k(c, nchk);
   const int nl = nchk / k;
   T* valt = static_cast<T*>(c->valt);
@@ -771,12 +765,8 @@ petto_status ensure_tuning(petto_ctx* c, hipStream_t s, int nchk) {
   TuneChoice choice;
   double best = 1e300;
   if (three) {
-    // the register-column tilings run FP32 sweeps only
-    const int cands32[] = {1, 2, 3, 4, 5};
-    const int cands64[] = {1, 2, 3};
-    const bool fp64 = c->prec == PETTO_FP64;
-    for (int q = 0; q < (fp64 ? 3 : 5); ++q) {
-      const int t = fp64 ? cands64[q] : cands32[q];
+    const int cands[] = {1, 2, 3};
+    for (int t : cands) {
       c->geom.tile3d = t;
       double ms = 0.0;
       PETTO_TRY(time_choice<T>(c, s, u, ua, v, b, 20, &ms));
@@ -1208,17 +1198,6 @@ petto_status petto_create(const petto_problem* probs, int32_t nprob, int32_t pre
     c->max_cells = c->ncell;
     c->state_off = {0, c->nstate};
     c->cell_off = {0, c->ncell};
-    if (p.ndim == 3) {
-      // the layers a plain 3D sweep reads the load on (it is zero elsewhere)
-      const long S = (long)(p.n[0] + 1) * (p.n[1] + 1);
-      const long L = (long)p.n[2] + 1;
-      for (size_t q = 0; q < F.size(); ++q) {
-        if (F[q] == 0.0) continue;
-        const int k = (int)(((long)q / S) % L);
-        c->load_k0 = std::min(c->load_k0, k);
-        c->load_k1 = std::max(c->load_k1, k);
-      }
-    }
     ElGeom& g = c->geom;
     g.nx = p.n[0];
     g.ny = p.n[1];
@@ -1513,12 +1492,9 @@ petto_status petto_time_sweeps(petto_ctx* ctx, int32_t launches, void* stream, d
   launch_fill<float>(c->b32, c->nstate, 0.f, s);
   const float* E = static_cast<const float*>(c->E);
   const int k = c->physics == PETTO_ELASTIC && c->ndim == 3 ? 1 : (c->blocking > 0 ? c->blocking : 1);
-  // the right-hand side the last solve swept with: the FP32 defect (refined mode)
-  // or the load (plain mode, which 3D sweeps read on the loaded layers only)
-  const float* bt = (!c->last_refine && c->Ft != nullptr) ? static_cast<const float*>(c->Ft) : c->b32;
   const int n = launches + (launches & 1);           // even: the state ends where it began
   auto run = [&](int nl) {
-    if (c->physics == PETTO_ELASTIC) elastic_sweeps<float>(c, s, u, ua, v, E, bt, c->st_t, nl * k);
+    if (c->physics == PETTO_ELASTIC) elastic_sweeps<float>(c, s, u, ua, v, E, c->b32, c->st_t, nl * k);
     else heat_sweeps<float>(c, s, u, ua, v, E, nullptr, c->st_t, nl * k, false, c->ctl + 2);
   };
   run(2);
@@ -1539,8 +1515,7 @@ petto_status petto_set_tile3d(petto_ctx* ctx, int32_t t) {
   if (ctx == nullptr) return fail(PETTO_ERR_INVALID, "ctx is NULL");
   if (ctx->physics != PETTO_ELASTIC || ctx->ndim != 3)
     return fail(PETTO_ERR_INVALID, "the 3D tiling applies to 3D elastic contexts");
-  if (t < 0 || t > 5) return fail(PETTO_ERR_INVALID, "unsupported 3D tiling %d", t);
-  if (t >= 4 && ctx->prec != PETTO_FP32) return fail(PETTO_ERR_INVALID, "3D tilings 4 and 5 are FP32 only");
+  if (t < 0 || t > 3) return fail(PETTO_ERR_INVALID, "unsupported 3D tiling %d", t);
   ctx->tuned3d = t != 0;
   if (t == 0) t = el3d_choose_tiling(ctx->geom, ctx->prec == PETTO_FP64, ctx->ncu);
   ctx->geom.tile3d = t;
@@ -1557,7 +1532,6 @@ petto_status petto_apt_solve(petto_ctx* ctx, const void* phi, void* u, void* v, 
   if (phi == nullptr || u == nullptr || v == nullptr) return fail(PETTO_ERR_INVALID, "phi, u and v must be non-NULL");
   PETTO_TRY(check_apt_params(ctx, params));
   hipStream_t s = static_cast<hipStream_t>(stream);
-  ctx->last_refine = params->refine != 0;
   if (ctx->timing) {
     ctx->timed_ms = 0.0;
     ctx->timed_sweeps = 0;

@@ -39,6 +39,7 @@ def main():
     ap.add_argument("--sweeps", type=int, default=2000)
     ap.add_argument("--check-every", type=int, default=100)
     ap.add_argument("--blocking", type=int, default=0, help="sweeps per launch (0: autotune)")
+    ap.add_argument("--tile3d", type=int, default=0, help="3D sweep tiling (0: autotune)")
     ap.add_argument("--copy-mib", type=int, default=256)
     a = ap.parse_args()
     import numpy as np
@@ -50,6 +51,8 @@ def main():
     probs = make(a.workload)
     ctx = Context(probs, "fp32")
     ctx.set_blocking(a.blocking)
+    if probs[0].ndim == 3 and probs[0].physics == W.ELASTIC:
+        ctx.set_tile3d(a.tile3d)
     if len(probs) == 1:
         phi = W.random_phi(probs[0], 1, 0.05, 1.0).ravel()
     else:

@@ -59,9 +59,9 @@ def mixed_elastic(ndim, variant=0):
         n = (66, 3, 2)
         side = (W.CLAMPED,) * 6
     else:
-        # n_x a multiple of 64 and n_y of 8: the face column and the face row fall
-        # to the halo waves of the register-column 3D sweep (with the corner);
-        # several z-tiles with a short top tile, clamped z sides (ghost layers)
+        # n_x a multiple of 64 and n_y of 8: the face column and the face row are
+        # the extra duties of the last x- and y-tiles (with the corner); several
+        # z-tiles with a short top tile, clamped z sides (ghost layers)
         n = (128, 16, 35)
         side = (W.CLAMPED, W.CLAMPED, W.ROLLER, W.CLAMPED, W.CLAMPED, W.CLAMPED)
     fixed = W._side_normal_fixed(ndim, n, side)

@@ -20,12 +20,9 @@ def _elastic_cases():
             ("multi3d", lambda: W.multimaterial3d(24, 10, 8)), ("duty3d", lambda: mixed_elastic(3, 3))]
 
 
-def _tilings(prob, prec="fp64"):
-    """3D contexts: every sweep tiling (the register-column tilings 4 and 5 run
-    FP32 sweeps only); 2D: the default."""
-    if prob.ndim != 3:
-        return [None]
-    return [1, 2, 3, 4, 5] if prec == "fp32" else [1, 2, 3]
+def _tilings(prob):
+    """3D contexts: every sweep tiling; 2D: the default."""
+    return [1, 2, 3] if prob.ndim == 3 else [None]
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
@@ -44,7 +41,7 @@ def test_elastic_residual_parity(name, make, prec):
     E = elastic.modulus(phi, prob)
     want = elastic.residual(u, E, prob, design.load_vector(prob))
     scale = np.abs(elastic.internal_force(np.abs(u), E, prob)).max() + np.abs(want).max()
-    for t in _tilings(prob, prec):
+    for t in _tilings(prob):
         if t is not None:
             ctx.set_tile3d(t)
         r = ctx.new_state()
@@ -92,7 +89,7 @@ def test_sweeps_parity(name, make, prec):
     with every sweep tiling)."""
     require_gpu()
     prob = make()
-    for t in _tilings(prob, prec):
+    for t in _tilings(prob):
         _sweeps_case(name, prob, prec, t)
 
 
