@@ -46,13 +46,20 @@ struct TbSmem {
 // the lane at the wave's edge receives zero (the zero ring around the window).
 template <int CTRL, typename T>
 __device__ __forceinline__ T wave_shift(T x) {
-  // bound control set: a lane whose source lies outside the wave receives zero
+  // bound control set: a lane whose source lies outside the wave receives zero.
+  // A lane shift must run with every lane of the wave active (a source lane that
+  // is masked off reads as zero), so the empty asm keeps the compiler from moving
+  // it into code that only some lanes execute (such as one arm of a per-lane
+  // select).
   if constexpr (sizeof(T) == 4) {
-    return __builtin_bit_cast(T, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), CTRL, 0xf, 0xf, true));
+    int r = __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), CTRL, 0xf, 0xf, true);
+    asm volatile("" : "+v"(r));
+    return __builtin_bit_cast(T, r);
   } else {
     const unsigned long long b = __builtin_bit_cast(unsigned long long, x);
-    const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)b, CTRL, 0xf, 0xf, true);
-    const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), CTRL, 0xf, 0xf, true);
+    int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)b, CTRL, 0xf, 0xf, true);
+    int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), CTRL, 0xf, 0xf, true);
+    asm volatile("" : "+v"(lo), "+v"(hi));
     return __builtin_bit_cast(T, ((unsigned long long)(unsigned)hi << 32) | (unsigned long long)(unsigned)lo);
   }
 }
