@@ -26,11 +26,10 @@ import workloads as W  # noqa: E402
 from oracle import design  # noqa: E402
 
 
-def cantilever_trajectory(nx, ny, steps, adapt):
+def trajectory(prob, steps, adapt):
     """`steps` design steps (Fig. 4 loop: relax to rho <= 1e-6, sensitivity, phase
-    update) of the 2D cantilever from its uniform initial design, recording the
-    design, state and compliance after every step."""
-    prob = W.cantilever2d(nx, ny)
+    update) from the problem's uniform initial design, recording the design,
+    state and compliance after every step."""
     phi = W.initial_phi(prob)
     u = np.zeros(prob.u_shape())
     ap = design.AptParams(theta=1.0, tol=1e-6, check_every=100, adapt=adapt)
@@ -44,7 +43,7 @@ def cantilever_trajectory(nx, ny, steps, adapt):
         out["energy2"].append(rec.energy2)
         out["iters"].append(rec.iters)
         out["rho"].append(rec.rho)
-        print(f"[oracle-job] {nx}x{ny} step {s + 1}/{steps}: {rec.iters} sweeps, rho {rec.rho:.3e}, "
+        print(f"[oracle-job] {prob.name} step {s + 1}/{steps}: {rec.iters} sweeps, rho {rec.rho:.3e}, "
               f"{time.time() - t0:.1f} s", file=sys.stderr, flush=True)
     return {k: np.asarray(v) for k, v in out.items()}
 
@@ -79,7 +78,10 @@ JOBS = {
     "heat_batch64_20": lambda: heat_batch_sweeps(20),
     # ten adaptive-damping design steps on a grid whose 64 x 32 sweep windows
     # include some strictly inside the grid (the multi-sweep kernel's fast path)
-    "cantilever2d_256x128_adapt_10": lambda: cantilever_trajectory(256, 128, 10, True),
+    "cantilever2d_256x128_adapt_10": lambda: trajectory(W.cantilever2d(256, 128), 10, True),
+    # the 3D cantilever and the two-phase 3D cantilever at 32 x 16 x 16
+    "cantilever3d_32x16x16_adapt_6": lambda: trajectory(W.cantilever3d(32, 16, 16), 6, True),
+    "multimaterial3d_32x16x16_adapt_4": lambda: trajectory(W.multimaterial3d(32, 16, 16), 4, True),
 }
 
 

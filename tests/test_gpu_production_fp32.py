@@ -91,7 +91,7 @@ def _gpu_trajectory(prob, steps, apt, capsys, label):
         assert st == L.OK, (s, si)
         hist.append(dict(iters=si[0]["iters"], rho=si[0]["rel_res"], phi=host(phi, phi0.shape),
                          u=host(u, prob.u_shape()), C=comp[0].item(), E2=comp[1].item(),
-                         volume=pi[0]["volume"][0]))
+                         volume=pi[0]["volume"][:phi0.shape[0]]))
     blocking = ctx.blocking()
     ctx.close()
     _say(capsys, f"{label}: GPU {steps} steps in {time.time() - t0:.1f} s, sweeps per launch {blocking}, "
@@ -110,8 +110,9 @@ def _compare(hist, ref, prob, label, capsys):
         for k, x in (("phi", e_phi), ("dphi", d_phi), ("u", e_u), ("C", e_c)):
             worst[k] = max(worst[k], x)
         assert e_phi < TOL32 and e_u < TOL32 and e_c < TOL32, (s, e_phi, e_u, e_c)
-        # the volume constraint holds exactly in the stored FP32 design
-        assert abs(h["volume"] - prob.vol_frac[0]) < 1e-6
+        # the volume constraints hold exactly in the stored FP32 design
+        for m, vol in enumerate(h["volume"]):
+            assert abs(vol - prob.vol_frac[m]) < 1e-6
     _say(capsys, f"{label}: worst over steps rel-L2(phi) {worst['phi']:.2e}, max|dphi| {worst['dphi']:.2e}, "
                  f"rel-L2(u) {worst['u']:.2e}, |dC|/C {worst['C']:.2e}")
 
@@ -157,6 +158,31 @@ def test_cantilever_256x128_trajectory_fp32_production(capsys, oracle_jobs):
         # checks apart; the sweep counts stay within a few percent
         assert abs(h["iters"] - int(n)) <= 0.03 * int(n), (h["iters"], int(n))
     _compare(hist, refs, prob, "256x128", capsys)
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("job,make,steps", [
+    pytest.param("cantilever3d_32x16x16_adapt_6", lambda: W.cantilever3d(32, 16, 16), 6,
+                 marks=pytest.mark.oracle_job("cantilever3d_32x16x16_adapt_6")),
+    pytest.param("multimaterial3d_32x16x16_adapt_4", lambda: W.multimaterial3d(32, 16, 16), 4,
+                 marks=pytest.mark.oracle_job("multimaterial3d_32x16x16_adapt_4"))])
+def test_3d_trajectory_fp32_production(job, make, steps, capsys, oracle_jobs):
+    """The 3D production loop (FP32 refined 3D sweeps with graphs and the timed
+    tiling, FP64 state, the 3D sensitivity and, for two phases, the bounded
+    second projection) against the oracle's own trajectory with its own stop
+    rule, computed in a child process."""
+    require_gpu()
+    prob = make()
+    announce(f"trajectory {job} fp32 refined adaptive")
+    oracle_jobs.start(job)
+    apt = dict(theta=1.0, tol=1e-6, check_every=100, adapt=True)
+    hist, _ = _gpu_trajectory(prob, steps, apt, capsys, job)
+    ref = oracle_jobs.result(job, progress=lambda m: _say(capsys, m))
+    refs = [dict(phi=ref["phi"][s], u=ref["u"][s], C=float(ref["compliance"][s])) for s in range(steps)]
+    _say(capsys, f"{job}: oracle sweeps {ref['iters'].tolist()}")
+    for h, n in zip(hist, ref["iters"]):
+        assert abs(h["iters"] - int(n)) <= 0.05 * int(n) + 200, (h["iters"], int(n))
+    _compare(hist, refs, prob, job, capsys)
 
 
 # ------------------------------------------------------------------ finite differences at 1024 x 512
