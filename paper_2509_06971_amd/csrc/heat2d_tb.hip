@@ -2,12 +2,16 @@
 //
 // Each work-list tile is the inner (64-2K) x (32-2K) cell block of one design; the
 // workgroup stages the 64 x 32 window around it (temperature, velocity, source,
-// conductivity, face conductances, Dirichlet terms), runs K sweeps with the
-// temperature exchanged through a double-buffered LDS plane (one barrier per
-// sweep) and writes back the inner block.  Same arithmetic as the one-sweep kernel
-// (heat_ops.hpp), so results are bit-identical for every K; the HBM traffic per
-// sweep drops about K times, which is what matters for batches larger than the
-// last-level cache.
+// conductivity, face conductances, Dirichlet terms), runs K sweeps and writes back
+// the inner block.  Same arithmetic as the one-sweep kernel (heat_ops.hpp), so
+// results are bit-identical for every K; the HBM traffic per sweep drops about K
+// times, which is what matters for batches larger than the last-level cache.
+//
+// Inside the window a wave owns RPW consecutive rows, one cell per lane and row:
+// the temperatures of the left and right neighbours are the adjacent lanes (DPP
+// wave shifts), those above and below inside the wave's rows are the thread's own
+// registers, and only each wave's first and last rows cross to the neighbouring
+// waves, through double-buffered LDS rows (one barrier per sweep).
 #include "heat_ops.hpp"
 #include "kernels.hpp"
 
@@ -18,45 +22,88 @@ namespace {
 
 constexpr int EX = 64, EY = 32;
 constexpr int NT = 512;
-constexpr int RSTEP = NT / EX;
-constexpr int PPT = EY / RSTEP;
-constexpr int PX = EX + 2, PY = EY + 2;
+constexpr int NW = NT / kWave;            // waves (8)
+constexpr int RPW = EY / NW;              // consecutive window rows per wave (4)
+static_assert(EX == kWave && RPW * NW == EY, "one lane per window column, whole rows per wave");
 
+// Rows exchanged between waves: slot w + 1 holds wave w's row; slots 0 and NW + 1
+// (below and above the window) stay zero, like the zero ring around the window.
 template <typename T>
 struct HTb {
-  T t[2][PY][PX];
-  T k[PY][PX];
-  double red[NT / kWave];
+  T t_last[2][NW + 2][EX];                // temperature of each wave's last row (sweep parity)
+  T t_first[2][NW + 2][EX];               // ... and of its first row
+  T k_last[NW + 2][EX];                   // conductivity of each wave's last / first row (staging)
+  T k_first[NW + 2][EX];
+  double red[NW];
 };
+
+// Value of the lane one to the left (lane - 1) or right (lane + 1); the lane at
+// the wave's edge reads zero (bound control).  A lane shift must run with every
+// lane of the wave active (a masked-off source lane reads as zero), so the empty
+// asm keeps the compiler from moving it into code that only some lanes execute.
+template <int CTRL, typename T>
+__device__ __forceinline__ T wave_shift(T x) {
+  if constexpr (sizeof(T) == 4) {
+    int r = __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), CTRL, 0xf, 0xf, true);
+    asm volatile("" : "+v"(r));
+    return __builtin_bit_cast(T, r);
+  } else {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, x);
+    int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)b, CTRL, 0xf, 0xf, true);
+    int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), CTRL, 0xf, 0xf, true);
+    asm volatile("" : "+v"(lo), "+v"(hi));
+    return __builtin_bit_cast(T, ((unsigned long long)(unsigned)hi << 32) | (unsigned long long)(unsigned)lo);
+  }
+}
+template <typename T>
+__device__ __forceinline__ T from_left(T x) { return wave_shift<0x138>(x); }   // wave_shr:1
+template <typename T>
+__device__ __forceinline__ T from_right(T x) { return wave_shift<0x130>(x); }  // wave_shl:1
 
 // K sweeps on the staged window.  Sweep k updates rows [k+1, EY-k-1) only: the
 // rows outside lie beyond the dependency cone of the written rows [K, EY-K)
-// (one row per wave, so the skip is wave-uniform), and rows a sweep skips are
-// never read by a row it updates.  FAST: every window position is a cell.
+// (a row lies in one wave, so the skip is wave-uniform), and rows a sweep skips
+// are never read by a row it updates.  FAST: every window position is a cell.
 template <typename T, int K, bool CHECK, bool FAST>
-__device__ __forceinline__ void heat_tb_sweeps(HTb<T>& sm, T (&tt)[PPT], T (&vv)[PPT], const T (&bb)[PPT],
-                                               const T (&kl)[PPT], const T (&kr)[PPT], const T (&kd)[PPT],
-                                               const T (&ku)[PPT], const T (&dd)[PPT], const bool (&cell)[PPT],
-                                               int li, int lw, int c, T ca, T cc, T dt, double& acc) {
+__device__ __forceinline__ void heat_tb_sweeps(HTb<T>& sm, T (&tt)[RPW], T (&vv)[RPW], const T (&bb)[RPW],
+                                               const T (&kl)[RPW], const T (&kr)[RPW], const T (&kd)[RPW],
+                                               const T (&ku)[RPW], const T (&dd)[RPW], const bool (&cell)[RPW],
+                                               int li, int w, T ca, T cc, T dt, double& acc) {
+  const int l0 = w * RPW;
   for (int k = 0; k < K; ++k) {
     const int cur = k & 1;
+    const T t_below = sm.t_last[cur][w][li];       // row l0 - 1
+    const T t_above = sm.t_first[cur][w + 2][li];  // row l0 + RPW
+    // every row's new temperature from the old ones (Jacobi), then the update
+    T tn[RPW], vn[RPW];
 #pragma unroll
-    for (int s = 0; s < PPT; ++s) {
-      const int lj = lw + s * RSTEP, r = lj + 1;
+    for (int s = 0; s < RPW; ++s) {
+      const int lj = l0 + s;
+      const T t_l = from_left(tt[s]);
+      const T t_r = from_right(tt[s]);
+      tn[s] = tt[s];
+      vn[s] = vv[s];
       if (lj < k + 1 || lj >= EY - k - 1) continue;
-      const T rr = heat::residual<T>(bb[s], tt[s], kl[s], sm.t[cur][r][c - 1], kr[s], sm.t[cur][r][c + 1], kd[s],
-                                     sm.t[cur][r - 1][c], ku[s], sm.t[cur][r + 1][c], dd[s]);
-      T un = tt[s], vn = vv[s];
-      heat::update<T>(ca, cc, dt, rr, un, vn);
+      const T t_d = s > 0 ? tt[s > 0 ? s - 1 : 0] : t_below;
+      const T t_u = s + 1 < RPW ? tt[s + 1 < RPW ? s + 1 : s] : t_above;
+      const T rr = heat::residual<T>(bb[s], tt[s], kl[s], t_l, kr[s], t_r, kd[s], t_d, ku[s], t_u, dd[s]);
+      T un = tt[s], v2 = vv[s];
+      heat::update<T>(ca, cc, dt, rr, un, v2);
       const bool live = FAST || cell[s];
-      tt[s] = live ? un : tt[s];
-      vv[s] = live ? vn : vv[s];
+      tn[s] = live ? un : tt[s];
+      vn[s] = live ? v2 : vv[s];
       if (CHECK && k == K - 1) {
         const bool inner = li >= K && li < EX - K && lj >= K && lj < EY - K && live;
         acc += inner ? (double)rr * (double)rr : 0.0;
       }
-      sm.t[cur ^ 1][r][c] = tt[s];
     }
+#pragma unroll
+    for (int s = 0; s < RPW; ++s) {
+      tt[s] = tn[s];
+      vv[s] = vn[s];
+    }
+    sm.t_last[cur ^ 1][w + 1][li] = tt[RPW - 1];
+    sm.t_first[cur ^ 1][w + 1][li] = tt[0];
     __syncthreads();
   }
 }
@@ -74,24 +121,28 @@ __global__ __launch_bounds__(NT) void heat2d_tb_kernel(HeatSweep<T> A) {
   const HeatDesign D = A.des[tl.design];
   __shared__ HTb<T> sm;
   const int ie = tl.i0 - K, je = tl.j0 - K;
-  // one window row per wave: the row index is wave-uniform (scalar branches)
-  const int li = threadIdx.x % EX, lw = __builtin_amdgcn_readfirstlane(threadIdx.x / EX);
-  const int c = li + 1, i = ie + li;
+  // lane = window column; the wave index is wave-uniform (scalar branches)
+  const int li = threadIdx.x % EX, w = __builtin_amdgcn_readfirstlane(threadIdx.x / EX);
+  const int l0 = w * RPW;
+  const int i = ie + li;
   const uint8_t* dir = A.dir + D.dir_off;
 
-  for (int q = threadIdx.x; q < 2 * PX + 2 * EY; q += NT) {
-    int r, cc;
-    if (q < 2 * PX) { r = q < PX ? 0 : PY - 1; cc = q % PX; }
-    else { const int t = q - 2 * PX; r = 1 + t / 2; cc = (t & 1) ? PX - 1 : 0; }
-    sm.t[0][r][cc] = T(0);
-    sm.t[1][r][cc] = T(0);
-    sm.k[r][cc] = T(0);
+  // the rows below and above the window are zero
+  if (w == 0) {
+    sm.t_last[0][0][li] = T(0);
+    sm.t_last[1][0][li] = T(0);
+    sm.k_last[0][li] = T(0);
   }
-  T tt[PPT], vv[PPT], bb[PPT], kc[PPT], dd[PPT];
-  bool cell[PPT];
+  if (w == NW - 1) {
+    sm.t_first[0][NW + 1][li] = T(0);
+    sm.t_first[1][NW + 1][li] = T(0);
+    sm.k_first[NW + 1][li] = T(0);
+  }
+  T tt[RPW], vv[RPW], bb[RPW], kc[RPW], dd[RPW];
+  bool cell[RPW];
 #pragma unroll
-  for (int s = 0; s < PPT; ++s) {
-    const int lj = lw + s * RSTEP, j = je + lj;
+  for (int s = 0; s < RPW; ++s) {
+    const int j = je + l0 + s;
     cell[s] = i >= 0 && i < D.nx && j >= 0 && j < D.ny;
     tt[s] = vv[s] = bb[s] = kc[s] = dd[s] = T(0);
     if (cell[s]) {
@@ -103,28 +154,38 @@ __global__ __launch_bounds__(NT) void heat2d_tb_kernel(HeatSweep<T> A) {
       const int nd = (i == 0 || j == 0 || i == D.nx - 1 || j == D.ny - 1) ? heat::dirichlet_count(dir, D.nx, D.ny, i, j) : 0;
       dd[s] = T(2 * nd) * kc[s];
     }
-    sm.t[0][lj + 1][c] = tt[s];
-    sm.k[lj + 1][c] = kc[s];
   }
+  sm.t_last[0][w + 1][li] = tt[RPW - 1];
+  sm.t_first[0][w + 1][li] = tt[0];
+  sm.k_last[w + 1][li] = kc[RPW - 1];
+  sm.k_first[w + 1][li] = kc[0];
   if (all_done || done) return;   // uniform over the workgroup, before its first barrier
   __syncthreads();
-  T kl[PPT], kr[PPT], kd[PPT], ku[PPT];
+  T kl[RPW], kr[RPW], kd[RPW], ku[RPW];
+  {
+    const T k_below = sm.k_last[w][li];
+    const T k_above = sm.k_first[w + 2][li];
 #pragma unroll
-  for (int s = 0; s < PPT; ++s) {
-    const int lj = lw + s * RSTEP, j = je + lj, r = lj + 1;
-    kl[s] = heat::face<T>(kc[s], sm.k[r][c - 1], i > 0);
-    kr[s] = heat::face<T>(kc[s], sm.k[r][c + 1], i < D.nx - 1);
-    kd[s] = heat::face<T>(kc[s], sm.k[r - 1][c], j > 0);
-    ku[s] = heat::face<T>(kc[s], sm.k[r + 1][c], j < D.ny - 1);
+    for (int s = 0; s < RPW; ++s) {
+      const int j = je + l0 + s;
+      const T k_l = from_left(kc[s]);
+      const T k_r = from_right(kc[s]);
+      const T k_d = s > 0 ? kc[s > 0 ? s - 1 : 0] : k_below;
+      const T k_u = s + 1 < RPW ? kc[s + 1 < RPW ? s + 1 : s] : k_above;
+      kl[s] = heat::face<T>(kc[s], k_l, i > 0);
+      kr[s] = heat::face<T>(kc[s], k_r, i < D.nx - 1);
+      kd[s] = heat::face<T>(kc[s], k_d, j > 0);
+      ku[s] = heat::face<T>(kc[s], k_u, j < D.ny - 1);
+    }
   }
   // a window inside its design: every position is a cell (no selects)
   const bool inner_window = ie >= 0 && je >= 0 && ie + EX <= D.nx && je + EY <= D.ny;
   double acc = 0.0;
-  if (inner_window) heat_tb_sweeps<T, K, CHECK, true>(sm, tt, vv, bb, kl, kr, kd, ku, dd, cell, li, lw, c, ca, cc, dt, acc);
-  else heat_tb_sweeps<T, K, CHECK, false>(sm, tt, vv, bb, kl, kr, kd, ku, dd, cell, li, lw, c, ca, cc, dt, acc);
+  if (inner_window) heat_tb_sweeps<T, K, CHECK, true>(sm, tt, vv, bb, kl, kr, kd, ku, dd, cell, li, w, ca, cc, dt, acc);
+  else heat_tb_sweeps<T, K, CHECK, false>(sm, tt, vv, bb, kl, kr, kd, ku, dd, cell, li, w, ca, cc, dt, acc);
 #pragma unroll
-  for (int s = 0; s < PPT; ++s) {
-    const int lj = lw + s * RSTEP, j = je + lj;
+  for (int s = 0; s < RPW; ++s) {
+    const int lj = l0 + s, j = je + lj;
     if (!cell[s] || li < K || li >= EX - K || lj < K || lj >= EY - K) continue;
     const long g = D.off + (long)j * D.nx + i;
     A.uout[g] = tt[s];
