@@ -79,6 +79,13 @@ __device__ __forceinline__ void sto(T* __restrict__ base, unsigned off, T v) {
   asm volatile("" : "+v"(off));
   *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + off) = v;
 }
+// The same for an offset that only this access reads: the asm acts on the
+// variable in place (no copy), and the access takes it as it is.
+__device__ __forceinline__ void opaque(unsigned& x) { asm volatile("" : "+v"(x)); }
+template <typename T>
+__device__ __forceinline__ T ldr(const T* __restrict__ base, unsigned off) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + off);
+}
 
 // Bits of a thread's own-position word.
 enum : unsigned {
@@ -171,7 +178,7 @@ __device__ __forceinline__ bool wave_has_entry(int e) {
 template <typename T, int TY>
 __device__ __forceinline__ void fetch_plane(const ElGeom& g, const T* __restrict__ ux, const T* __restrict__ uy,
                                             const T* __restrict__ uz, const T* __restrict__ E, long S, long SE,
-                                            const Entry<T> (&en)[Plane<T, TY>::NE], int k, Plane<T, TY>& P) {
+                                            Entry<T> (&en)[Plane<T, TY>::NE], int k, Plane<T, TY>& P) {
   const int nz = g.nz;
   const int kxy = k < 0 ? 0 : (k >= nz ? nz - 1 : k);
   const int kzs = k < 0 ? 0 : (k > nz ? nz : k);
@@ -182,10 +189,14 @@ __device__ __forceinline__ void fetch_plane(const ElGeom& g, const T* __restrict
 #pragma unroll
   for (int e = 0; e < Plane<T, TY>::NE; ++e) {
     if (!wave_has_entry<TY>(e)) continue;
-    P.v[e][0] = ldo(bx, en[e].ox);
-    P.v[e][1] = ldo(by, en[e].oy);
-    P.v[e][2] = ldo(bz, en[e].oz);
-    P.v[e][3] = ldo(be, en[e].oe);
+    opaque(en[e].ox);
+    opaque(en[e].oy);
+    opaque(en[e].oz);
+    opaque(en[e].oe);
+    P.v[e][0] = ldr(bx, en[e].ox);
+    P.v[e][1] = ldr(by, en[e].oy);
+    P.v[e][2] = ldr(bz, en[e].oz);
+    P.v[e][3] = ldr(be, en[e].oe);
   }
 }
 
@@ -417,9 +428,10 @@ __global__ __launch_bounds__(TX * TY, 4) void el3d_stream_kernel(ElGeom g, ElSwe
   const int qo = b * LX + a;
   // one layer; the buffer parity is a compile-time constant (the loop below is
   // unrolled by two), so every LDS access has a constant offset
-  auto layer = [&](auto parity, int k) {
+  auto layer = [&](auto parity, auto fetch, int k) {
     constexpr int cur = decltype(parity)::value;
     constexpr int up = cur ^ 1;
+    constexpr bool FETCH = decltype(fetch)::value;
     // plane k+1 into LDS (its buffer was last read before the previous barrier)
     store_plane<T, TY>(g, P, en, k + 1, up, sm);
     // own velocity / right-hand side of layer k (issued early, used after the stresses)
@@ -444,7 +456,7 @@ __global__ __launch_bounds__(TX * TY, 4) void el3d_stream_kernel(ElGeom g, ElSwe
     }
     __syncthreads();
     // fetch plane k+2 while this layer computes
-    if (k + 1 < kend) fetch_plane<T, TY>(g, ux, uy, uz, A.E, S, SE, en, k + 2, P);
+    if (FETCH) fetch_plane<T, TY>(g, ux, uy, uz, A.E, S, SE, en, k + 2, P);
     const T uo[3] = {(&sm.u[cur][0][0][0])[qo], (&sm.u[cur][1][0][0])[qo], (&sm.u[cur][2][0][0])[qo]};
     T uxe = T(0), uye = T(0);
     if (edge_duty) {
@@ -462,25 +474,45 @@ __global__ __launch_bounds__(TX * TY, 4) void el3d_stream_kernel(ElGeom g, ElSwe
     const T* U0 = &sm.u[cur][0][0][0];
     const T* U1 = &sm.u[cur][1][0][0];
     const T* U2 = &sm.u[cur][2][0][0];
+    const T* U0u = &sm.u[up][0][0][0];
+    const T* U1u = &sm.u[up][1][0][0];
     const T* U2u = &sm.u[up][2][0][0];
     const T* EC = &sm.e[cur][0][0];
+    const T* EU = &sm.e[up][0][0];
 #pragma unroll
     for (int e = 0; e < NE; ++e) {
       if (!wave_has_entry<TY>(e)) continue;
       const int q = en[e].q;
-      const T ev = EC[q];
-      const T exx = (U0[q + 1] - U0[q]) * rh;
-      const T eyy = (U1[q + LX] - U1[q]) * rh;
-      const T ezz = (U2u[q] - U2[q]) * rh;
+      // every LDS operand of the entry is read before any is used, so that the
+      // reads are in flight together (the scheduling barrier keeps the compiler
+      // from interleaving each read with its use)
+      const T ev = EC[q], e_w = EC[q - 1], e_s = EC[q - LX], e_sw = EC[q - LX - 1];
+      const T eu = EU[q], eu_w = EU[q - 1], eu_s = EU[q - LX];
+      const T u0 = U0[q], u0e = U0[q + 1], u0s = U0[q - LX];
+      const T u1 = U1[q], u1n = U1[q + LX], u1w = U1[q - 1];
+      const T u2 = U2[q], u2u = U2u[q], u2uw = U2u[q - 1], u2us = U2u[q - LX];
+      const T u0u = U0u[q], u1u = U1u[q];
+      __builtin_amdgcn_sched_barrier(0);
+      const T exx = (u0e - u0) * rh;
+      const T eyy = (u1n - u1) * rh;
+      const T ezz = (u2u - u2) * rh;
       T sxx, syy, szz;
       el3d::normal_stress<T>(ev * lam0, T(2) * (ev * mu0), exx, eyy, ezz, sxx, syy, szz);
-      const T m = (cxy * (((EC[q - LX - 1] + EC[q - LX]) + EC[q - 1]) + ev)) * en[e].fxy;
-      const T gam = el3d::shear_strain<T>(U0[q], U0[q - LX], U1[q], U1[q - 1], rh);
+      const T m = (cxy * (((e_sw + e_s) + e_w) + ev)) * en[e].fxy;
+      const T gam = el3d::shear_strain<T>(u0, u0s, u1, u1w, rh);
+      // xz edge (i, j+1/2, k+1): cells (i-1..i, j, k..k+1); yz edge (i+1/2, j, k+1)
+      const T fxz = fmin(en[e].fxz * s1, T(2));
+      const T fyz = fmin(en[e].fyz * s1, T(2));
+      const T mxz = (cz * (((e_w + ev) + eu_w) + eu)) * fxz;
+      const T gxz = el3d::shear_strain<T>(u0u, u0, u2u, u2uw, rh);
+      const T myz = (cz * (((e_s + ev) + eu_s) + eu)) * fyz;
+      const T gyz = el3d::shear_strain<T>(u1u, u1, u2u, u2us, rh);
       (&sm.sxx[0][0])[q] = sxx;
       (&sm.syy[0][0])[q] = syy;
       (&sm.szz[0][0])[q] = szz;
       (&sm.txy[0][0])[q] = m * gam;
-      xz_yz_entry<T, TY>(en[e], cur, up, up, cz, s1, rh, sm);
+      (&sm.txz[up][0][0])[q] = mxz * gxz;
+      (&sm.tyz[up][0][0])[q] = myz * gyz;
     }
     __syncthreads();
     // residuals and update of the own position at layer k (reads stress planes only)
@@ -608,10 +640,23 @@ __global__ __launch_bounds__(TX * TY, 4) void el3d_stream_kernel(ElGeom g, ElSwe
       }
     }
   };
-  for (int k = k0; k < kend; k += 2) {
-    layer(std::integral_constant<int, 0>(), k);
-    if (k + 1 >= kend) break;
-    layer(std::integral_constant<int, 1>(), k + 1);
+  // Every layer but the last fetches plane k+2, unconditionally: the wait for
+  // the own velocity and right-hand side (loaded before the fetch) then leaves
+  // the fetch in flight; behind a branch it would have to wait for it too.
+  using P0 = std::integral_constant<int, 0>;
+  using P1 = std::integral_constant<int, 1>;
+  using F1 = std::true_type;
+  using F0 = std::false_type;
+  int k = k0;
+  for (; k + 2 < kend; k += 2) {
+    layer(P0(), F1(), k);
+    layer(P1(), F1(), k + 1);
+  }
+  if (kend - k == 2) {
+    layer(P0(), F1(), k);
+    layer(P1(), F0(), k + 1);
+  } else {
+    layer(P0(), F0(), k);
   }
   if (top_tile) {
     // the buffer parity of layer nz follows that of the last layer run
