@@ -312,12 +312,15 @@ def run_ttd(workload, nx, ny, steps, modes, theta, tol, adapt, max_iter, progres
         sweeps, hist, capped = 0, [], 0
         torch.cuda.synchronize()
         t0 = time.perf_counter()
+        t_last = t0
         for s in range(steps):
             st, si, pi, _ = ctx.step(phi, u, v, g, vol_frac=prob.vol_frac, compliance=comp, apt=apt)
             sweeps += si[0]["iters"]
             hist.append(si[0]["iters"])
             capped += si[0]["status"] == 1
-            if progress and ((s + 1) % 10 == 0 or s + 1 == steps):
+            # a line every 10 steps, and after any step that ends a minute after the last line
+            if progress and ((s + 1) % 10 == 0 or s + 1 == steps or time.perf_counter() - t_last > 60.0):
+                t_last = time.perf_counter()
                 print(f"[ttd] {name} {mode} step {s + 1}/{steps}: {si[0]['iters']} sweeps, "
                       f"rho {si[0]['rel_res']:.3g}, theta {si[0]['theta']:.4g}, {time.perf_counter() - t0:.1f} s",
                       file=sys.stderr, flush=True)
