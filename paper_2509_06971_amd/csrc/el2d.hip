@@ -38,30 +38,55 @@ __device__ inline bool pinned(const uint32_t* pins, long k) {
   return pins != nullptr && ((pins[k >> 5] >> (k & 31)) & 1u);
 }
 
-// Stage u (+ ghosts) and E of positions [i0-1, i0+TX] x [j0-1, j0+TY].
+// Stage u (+ ghosts) and E of positions [i0-1, i0+TX] x [j0-1, j0+TY].  Every
+// staged value is one load from an index inside the arrays (a ghost reads the
+// value it reflects, a slot outside reads element 0) and a select: +value,
+// -value (reflected ghost of a clamped side) or zero.  All loads of a thread
+// are issued before the first is used, so the tile costs one memory round trip.
 template <typename T>
 __device__ inline void load_tile(const ElGeom& g, const T* __restrict__ u, const T* __restrict__ E,
                                  int i0, int j0, T (*sux)[LX], T (*suy)[LX], T (*sE)[LX]) {
+  constexpr int NS = (LY * LX + kBlock - 1) / kBlock;
   const int nx = g.nx, ny = g.ny, px = g.px;
   const long pl = g.plane;
-  for (int idx = threadIdx.x; idx < LY * LX; idx += kBlock) {
+  T vx[NS], vy[NS], ve[NS];
+  int sx[NS], sy[NS];      // +1 value, -1 reflected ghost, 0 zero
+  bool se[NS];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const int idx0 = (int)threadIdx.x + s * kBlock;
+    const int idx = idx0 < LY * LX ? idx0 : LY * LX - 1;
     const int lj = idx / LX, li = idx - lj * LX;
     const int i = i0 - 1 + li, j = j0 - 1 + lj;
-    T vx = T(0), vy = T(0), e = T(0);
+    // u_x(i, j): x-face i in [0, nx], rows j in [0, ny); ghost rows -1 and ny
+    long px_src = 0;
+    sx[s] = 0;
     if (i >= 0 && i <= nx) {
-      if (j >= 0 && j < ny) vx = u[(long)j * px + i];
-      else if (j == -1) { if (g.clamp[2]) vx = -u[i]; }
-      else if (j == ny) { if (g.clamp[3]) vx = -u[(long)(ny - 1) * px + i]; }
+      if (j >= 0 && j < ny) { px_src = (long)j * px + i; sx[s] = 1; }
+      else if (j == -1) { px_src = i; sx[s] = g.clamp[2] ? -1 : 0; }
+      else if (j == ny) { px_src = (long)(ny - 1) * px + i; sx[s] = g.clamp[3] ? -1 : 0; }
     }
+    // u_y(i, j): y-face j in [0, ny], columns i in [0, nx); ghost columns -1 and nx
+    long py_src = 0;
+    sy[s] = 0;
     if (j >= 0 && j <= ny) {
-      if (i >= 0 && i < nx) vy = u[pl + (long)j * px + i];
-      else if (i == -1) { if (g.clamp[0]) vy = -u[pl + (long)j * px]; }
-      else if (i == nx) { if (g.clamp[1]) vy = -u[pl + (long)j * px + nx - 1]; }
+      if (i >= 0 && i < nx) { py_src = (long)j * px + i; sy[s] = 1; }
+      else if (i == -1) { py_src = (long)j * px; sy[s] = g.clamp[0] ? -1 : 0; }
+      else if (i == nx) { py_src = (long)j * px + nx - 1; sy[s] = g.clamp[1] ? -1 : 0; }
     }
-    if (E != nullptr && i >= 0 && i < nx && j >= 0 && j < ny) e = E[(long)j * nx + i];
-    sux[lj][li] = vx;
-    suy[lj][li] = vy;
-    if (E != nullptr) sE[lj][li] = e;
+    se[s] = E != nullptr && i >= 0 && i < nx && j >= 0 && j < ny;
+    vx[s] = u[px_src];
+    vy[s] = u[pl + py_src];
+    ve[s] = E != nullptr ? E[se[s] ? (long)j * nx + i : 0] : T(0);
+  }
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const int idx = (int)threadIdx.x + s * kBlock;
+    if (idx >= LY * LX) continue;
+    const int lj = idx / LX, li = idx - lj * LX;
+    sux[lj][li] = sx[s] == 0 ? T(0) : (sx[s] < 0 ? -vx[s] : vx[s]);
+    suy[lj][li] = sy[s] == 0 ? T(0) : (sy[s] < 0 ? -vy[s] : vy[s]);
+    if (E != nullptr) sE[lj][li] = se[s] ? ve[s] : T(0);
   }
 }
 
