@@ -18,6 +18,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libpetto.so")
+PROBE = os.path.join(PKG, "stream_probe")
 SOURCES = ["petto.hip", "el2d.hip", "el2d_tb.hip", "el3d.hip", "el3d_stream.hip", "heat2d.hip", "heat2d_tb.hip", "control.hip", "phase.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -54,6 +55,13 @@ def build(verbose: bool = False) -> str:
         if p.returncode != 0:
             raise RuntimeError(f"link failed:\n{p.stderr}")
         os.replace(out_tmp, LIB)
+        # the streaming bandwidth probe: a standalone program, not linked into the library
+        probe_tmp = PROBE + ".tmp"
+        cmd = [HIPCC] + FLAGS + [os.path.join(CSRC, "stream_probe.hip"), "-o", probe_tmp]
+        p = subprocess.run(cmd, capture_output=True, text=True)
+        if p.returncode != 0:
+            raise RuntimeError(f"hipcc failed on stream_probe.hip:\n{p.stderr}")
+        os.replace(probe_tmp, PROBE)
     finally:
         shutil.rmtree(tmp, ignore_errors=True)
     return LIB
