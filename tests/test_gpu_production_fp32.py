@@ -6,6 +6,9 @@ number of sweeps per launch; the sensitivity then reads the FP64 state.  The
 tolerance on designs, states and compliance is 1e-4 relative (the FP32 target of
 the configurations); the observed agreement is printed.
 
+A batch of heat designs runs the same production loop (one context, every
+design stopping on its own check).
+
 Also here: direct parity of the 2D sensitivity kernel when its state or its
 arithmetic is FP32, and the finite-difference check of the sensitivity on 8
 seeded cells of the 1024 x 512 cantilever, at the initial design and after 20
@@ -134,6 +137,62 @@ def test_cantilever_64x32_trajectory_fp32_production(capsys):
         assert rec.rho <= 1e-6
         ref.append(dict(phi=ph, u=uo, C=rec.compliance))
     _compare(hist, ref, prob, "64x32", capsys)
+
+
+@pytest.mark.timeout(600)
+def test_heat_batch_trajectory_fp32_production(capsys):
+    """Six heat designs of uneven size in one context (their own Dirichlet patches,
+    24-80 cells a side): 8 production design steps (FP32 refined sweeps, graphs,
+    autotuned sweeps per launch, every design stopping on its own check) against
+    the oracle run design by design, replaying each design's sweep counts."""
+    require_gpu()
+    probs, _, _ = W.heat_batch_small()
+    steps = 8
+    announce(f"trajectory heat batch ({len(probs)} designs) fp32 refined, {steps} steps")
+    ctx = context(probs, "fp32")
+    phi0 = [W.initial_phi(p) for p in probs]
+    phi = dev(np.concatenate([x.ravel() for x in phi0]), torch.float32)
+    u = ctx.new_state(torch.float64)
+    v = ctx.new_state()
+    g = ctx.new_cells()
+    comp = torch.zeros(2 * len(probs), dtype=torch.float64, device="cuda")
+    apt = dict(theta=1.0, tol=1e-6, check_every=100, refine=True, use_graph=True)
+    hist = []
+    t0 = time.time()
+    for s in range(steps):
+        st, si, pi, _ = ctx.step(phi, u, v, g, vol_frac=probs[0].vol_frac, compliance=comp, apt=apt)
+        assert st == L.OK, (s, si)
+        ph, uh, c = host(phi), host(u), comp.cpu().numpy()
+        rec = []
+        for d, p in enumerate(probs):
+            c0, c1 = ctx.offset(d, L.FIELD_CELL), ctx.offset(d + 1, L.FIELD_CELL)
+            s0, s1 = ctx.offset(d, L.FIELD_STATE), ctx.offset(d + 1, L.FIELD_STATE)
+            rec.append(dict(iters=si[d]["iters"], rho=si[d]["rel_res"], phi=ph[c0:c1].reshape(p.phi_shape()),
+                            u=uh[s0:s1].reshape(p.cell_shape()), C=float(c[2 * d]), volume=pi[d]["volume"][0]))
+        hist.append(rec)
+    ctx.close()
+    _say(capsys, f"heat batch: GPU {steps} steps in {time.time() - t0:.1f} s, sweeps per design and step "
+                 f"{[[h[d]['iters'] for h in hist] for d in range(len(probs))]}")
+    worst = dict(phi=0.0, u=0.0, C=0.0)
+    for d, p in enumerate(probs):
+        ph, uo = phi0[d], np.zeros(p.cell_shape())
+        for s in range(steps):
+            h = hist[s][d]
+            ph, uo, _, r = design.design_step(ph, uo, p, design.AptParams(theta=1.0, tol=1e-6, check_every=100),
+                                              n_iter=h["iters"])
+            # the GPU's FP64 check of its refined state met the tolerance, and the
+            # FP64 oracle after the same sweep count sits at it too: the FP32 sweeps
+            # reach a state 1e-4 close to the FP64 iteration's, whose residual at the
+            # stop can lie a little either side (one design ends 0.5 % above)
+            assert h["rho"] <= 1e-6, (d, s, h["rho"])
+            assert r.rho <= 1.02e-6, (d, s, r.rho)
+            e_phi, e_u = rel_l2(h["phi"], ph), rel_l2(h["u"], uo)
+            e_c = abs(h["C"] - r.compliance) / abs(r.compliance)
+            assert e_phi < TOL32 and e_u < TOL32 and e_c < TOL32, (d, s, e_phi, e_u, e_c)
+            assert abs(h["volume"] - p.vol_frac[0]) < 1e-6, (d, s, h["volume"])
+            worst = dict(phi=max(worst["phi"], e_phi), u=max(worst["u"], e_u), C=max(worst["C"], e_c))
+    _say(capsys, f"heat batch: worst over designs and steps rel-L2(phi) {worst['phi']:.2e}, "
+                 f"rel-L2(T) {worst['u']:.2e}, |dC|/C {worst['C']:.2e}")
 
 
 @pytest.mark.timeout(1500)
