@@ -138,22 +138,38 @@ __global__ __launch_bounds__(NT) void heat2d_tb_kernel(HeatSweep<T> A) {
     sm.t_first[1][NW + 1][li] = T(0);
     sm.k_first[NW + 1][li] = T(0);
   }
+  // Every load of every row is issued before any is used (a position outside
+  // the design reads the design's first cell and is zeroed afterwards), so the
+  // window costs one memory round trip; loads behind a per-row branch had each
+  // waited for the row before.  (The Dirichlet side tables are read only for
+  // cells on the design's boundary.)
   T tt[RPW], vv[RPW], bb[RPW], kc[RPW], dd[RPW];
+  int nd[RPW];
   bool cell[RPW];
 #pragma unroll
   for (int s = 0; s < RPW; ++s) {
     const int j = je + l0 + s;
     cell[s] = i >= 0 && i < D.nx && j >= 0 && j < D.ny;
-    tt[s] = vv[s] = bb[s] = kc[s] = dd[s] = T(0);
-    if (cell[s]) {
-      const long g = D.off + (long)j * D.nx + i;
-      tt[s] = A.uin[g];
-      vv[s] = A.v[g];
-      bb[s] = A.b != nullptr ? A.b[g] : T(D.fsrc);
-      kc[s] = A.k[g];
-      const int nd = (i == 0 || j == 0 || i == D.nx - 1 || j == D.ny - 1) ? heat::dirichlet_count(dir, D.nx, D.ny, i, j) : 0;
-      dd[s] = T(2 * nd) * kc[s];
-    }
+    const long g = D.off + (cell[s] ? (long)j * D.nx + i : 0L);
+    tt[s] = A.uin[g];
+    vv[s] = A.v[g];
+    bb[s] = A.b != nullptr ? A.b[g] : T(D.fsrc);
+    kc[s] = A.k[g];
+  }
+#pragma unroll
+  for (int s = 0; s < RPW; ++s) {
+    const int j = je + l0 + s;
+    nd[s] = (cell[s] && (i == 0 || j == 0 || i == D.nx - 1 || j == D.ny - 1))
+                ? heat::dirichlet_count(dir, D.nx, D.ny, i, j) : 0;
+  }
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int s = 0; s < RPW; ++s) {
+    tt[s] = cell[s] ? tt[s] : T(0);
+    vv[s] = cell[s] ? vv[s] : T(0);
+    bb[s] = cell[s] ? bb[s] : T(0);
+    kc[s] = cell[s] ? kc[s] : T(0);
+    dd[s] = cell[s] ? T(2 * nd[s]) * kc[s] : T(0);
   }
   sm.t_last[0][w + 1][li] = tt[RPW - 1];
   sm.t_first[0][w + 1][li] = tt[0];
