@@ -26,21 +26,35 @@ struct HSmem {
   double red[kBlock / kWave];
 };
 
+// Stage temperature and conductivity of cells [i0-1, i0+TX] x [j0-1, j0+TY]: a
+// slot outside the design reads the design's first cell and is zeroed by a
+// select, so every load of a thread is issued before the first is used (one
+// memory round trip for the tile).
 template <typename T>
 __device__ inline void load_heat_tile(const HeatDesign& D, const T* __restrict__ u,
                                       const T* __restrict__ kk, int i0, int j0, T (*st)[LX],
                                       T (*sk)[LX]) {
-  for (int idx = threadIdx.x; idx < LY * LX; idx += kBlock) {
+  constexpr int NS = (LY * LX + kBlock - 1) / kBlock;
+  T tv[NS], kv[NS];
+  bool in[NS];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const int idx0 = (int)threadIdx.x + s * kBlock;
+    const int idx = idx0 < LY * LX ? idx0 : LY * LX - 1;
     const int lj = idx / LX, li = idx - lj * LX;
     const int i = i0 - 1 + li, j = j0 - 1 + lj;
-    T tv = T(0), kv = T(0);
-    if (i >= 0 && i < D.nx && j >= 0 && j < D.ny) {
-      const long c = D.off + (long)j * D.nx + i;
-      tv = u[c];
-      if (kk != nullptr) kv = kk[c];
-    }
-    st[lj][li] = tv;
-    if (sk != nullptr) sk[lj][li] = kv;
+    in[s] = i >= 0 && i < D.nx && j >= 0 && j < D.ny;
+    const long c = D.off + (in[s] ? (long)j * D.nx + i : 0L);
+    tv[s] = u[c];
+    kv[s] = kk != nullptr ? kk[c] : T(0);
+  }
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const int idx = (int)threadIdx.x + s * kBlock;
+    if (idx >= LY * LX) continue;
+    const int lj = idx / LX, li = idx - lj * LX;
+    st[lj][li] = in[s] ? tv[s] : T(0);
+    if (sk != nullptr) sk[lj][li] = in[s] ? kv[s] : T(0);
   }
 }
 
